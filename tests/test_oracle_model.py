@@ -1,0 +1,97 @@
+"""Pins of the oracle's model pieces: RNG, lattice, exponentials, HS constants."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+
+def test_philox_matches_numpy(orc):
+    """Philox4x64-10 (Salmon et al. SC'11) against numpy's independent
+    implementation; numpy bumps the counter before producing a block."""
+    rng = np.random.default_rng(7)
+    cases = [((1, 0, 0, 0), (5, 7))]
+    for _ in range(50):
+        ctr = tuple(int(x) for x in rng.integers(0, 2**63, size=4))
+        if ctr[0] == 0:
+            ctr = (1,) + ctr[1:]
+        key = tuple(int(x) for x in rng.integers(0, 2**63, size=2))
+        cases.append((ctr, key))
+    for ctr, key in cases:
+        ref = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                               counter=np.array([ctr[0] - 1] + list(ctr[1:]), dtype=np.uint64))
+        want = ref.random_raw(4)
+        got = orc.philox(ctr, key)
+        assert np.array_equal(got, want), (ctr, key)
+    # known-answer vector for key (5,7), counter (1,0,0,0)
+    got = orc.philox((1, 0, 0, 0), (5, 7))
+    assert [hex(int(x)) for x in got] == ["0x2de0f782c87deea2", "0xb8acbd30539dad85",
+                                         "0xdc347efdf4a3a932", "0x1a9b27c5020252ac"]
+
+
+def test_initial_field_is_uniform_pm1(orc):
+    c = orc.Chain(8, 2.0, 0.25, 10.0, 0.5, 1504050900, 0, 3, 10)
+    h = c.field()
+    assert set(np.unique(h)) == {-1, 1}
+    # draw bit 63 of word 0 at counter (0, (l-1)N+i, 1, 0), key (seed+chain, inst)
+    w = orc.draw(1504050900 + 3, 0, 0, 5 * 64 + 7, 1)
+    assert h[5, 7] == (1 if (w >> 63) == 0 else -1)
+    assert abs(h.mean()) < 0.1
+
+
+def dispersion(L, t):
+    return np.array([-2 * t * (math.cos(2 * math.pi * (k % L) / L) + math.cos(2 * math.pi * (k // L) / L))
+                     for k in range(L * L)])
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 6])
+def test_hopping_spectrum_is_tight_binding(orc, L):
+    """eig(K) = eps_k = -2t(cos kx + cos ky) (the dispersion used with eq. (6));
+    for L = 2 this needs the doubled periodic bonds."""
+    K = orc.hopping(L, 0.25)
+    assert np.allclose(K, K.T)
+    ev = np.sort(np.linalg.eigvalsh(K))
+    assert np.max(np.abs(ev - np.sort(dispersion(L, 0.25)))) < 1e-14
+
+
+@pytest.mark.parametrize("dtau", [0.1, 0.5, 0.8, 2.0])
+def test_expm_against_scipy(orc, dtau):
+    K = orc.hopping(6, 0.25)
+    for s in (-dtau, dtau):
+        assert np.max(np.abs(orc.expm(K, s) - sla.expm(s * K))) < 1e-14
+    A = np.random.default_rng(1).standard_normal((7, 7))
+    assert np.max(np.abs(orc.expm(A, 1.3) - sla.expm(1.3 * A))) < 1e-12 * np.max(np.abs(sla.expm(1.3 * A)))
+
+
+@pytest.mark.parametrize("U,dtau", [(2.0, 0.5), (1.0, 0.4), (4.0, 0.125), (0.5, 0.8)])
+def test_hs_identity_per_site(orc, U, dtau):
+    """Discrete HS transformation of one site and slice: for every occupation
+    (n_up, n_dn), sum_{h=+-1} C e^{lambda h (n_up - n_dn)} equals
+    e^{-dtau U (n_up - 1/2)(n_dn - 1/2)} with C = e^{-dtau U / 4} / 2."""
+    lam = orc.hs_lambda(U, dtau)
+    C = math.exp(-dtau * U / 4) / 2
+    for nu, nd in itertools.product((0, 1), repeat=2):
+        lhs = sum(C * math.exp(lam * h * (nu - nd)) for h in (1, -1))
+        rhs = math.exp(-dtau * U * (nu - 0.5) * (nd - 0.5))
+        assert abs(lhs - rhs) < 1e-14 * rhs
+
+
+def test_bmat_order(orc):
+    """B_l = e^{-dtau K} diag(e^{sigma lambda h_l}): kinetic factor on the left."""
+    c = orc.Chain(4, 2.0, 0.25, 4.0, 0.5, 11, 0, 0, 4)
+    f = c.field()
+    Em = sla.expm(-0.5 * orc.hopping(4, 0.25))
+    for spin, sg in ((0, 1.0), (1, -1.0)):
+        B = c.bmat(3, spin)
+        ref = Em @ np.diag(np.exp(sg * c.lam * f[2]))
+        assert np.max(np.abs(B - ref)) < 1e-14
+
+
+def test_create_rejects_bad_arguments(orc):
+    with pytest.raises(ValueError):
+        orc.Chain(4, 2.0, 0.25, 4.1, 0.5, 1)       # beta/dtau not integral
+    with pytest.raises(ValueError):
+        orc.Chain(1, 2.0, 0.25, 4.0, 0.5, 1)
+    with pytest.raises(ValueError):
+        orc.Chain(4, -1.0, 0.25, 4.0, 0.5, 1)
