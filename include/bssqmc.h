@@ -1,0 +1,220 @@
+/*
+ * bssqmc.h -- C ABI of the MI355X (gfx950) BSS-QMC sweep library.
+ *
+ * The library samples the discrete Hubbard-Stratonovich Ising field h of the
+ * Trotter-decomposed partition function of the half-filled Hubbard model,
+ *   Z_dtau = sum_h det M_up[h] det M_dn[h]                  (paper, eq. (3))
+ * with M_sigma = I + B^sigma_Lambda ... B^sigma_1,
+ *   B^sigma_l = e^{-dtau K} diag(e^{sigma lambda h_{l,i}}),  cosh(lambda) = e^{dtau U/2},
+ * for H = -t sum_<ij>,sigma c^+_i c_j + U sum_i (n_up - 1/2)(n_dn - 1/2)
+ * (eq. (1)) on an L x L square lattice with periodic boundaries (Sec. 2),
+ * Lambda = beta/dtau slices (eq. (2)).  The Monte Carlo summation of eq. (3)
+ * yields the Green functions G_ij(tau_l) on the grid tau_l = l dtau in
+ * [0, beta] (Sec. 2, paragraph after eq. (3)); the library reports their
+ * momentum-resolved form and the double occupancy.
+ *
+ * One sweep visits l = 1..Lambda, i = 0..N-1 (N = L^2) in this fixed order;
+ * per proposal it forms the determinant ratio R = R_up R_dn with
+ * R_sigma = 1 + (1 - G_sigma,ii)(e^{-2 sigma lambda h_{l,i}} - 1) and accepts
+ * iff u < R (Metropolis; u from Philox4x64-10 keyed by (seed + chain,
+ * instance) at counter (sweep, (l-1) N + i, 0, 0), 53-bit uniform of word 0).
+ * Accepted flips update G by Sherman-Morrison, delayed to rank k; after each
+ * slice G is wrapped, G <- B_l G B_l^{-1}; every n_stab slices and at
+ * l = Lambda G is recomputed from the B chain by UDV/QR in FP64 and replaces
+ * the wrapped G.
+ *
+ * Conventions
+ *   site i = x + L*y; momentum index k = mx + L*my, k = 2 pi (mx, my)/L.
+ *   Matrices exchanged through this ABI are row-major FP64 host arrays.
+ *   Internal Green functions are G = <c c^+> (positive).  Reported G(tau, k)
+ *   has the paper's sign, G(tau) = -<T c(tau) c^+(0)> (eq. (4)).
+ *
+ * Ownership and threading
+ *   The library owns the context and all device state, except an optional
+ *   caller-provided workspace (bss_options.workspace), which must stay alive
+ *   until bss_destroy.  All other pointer arguments are caller-owned HOST
+ *   buffers.  bss_sweep / bss_step_slices are asynchronous on the context's
+ *   stream; every bss_get_* / bss_measure_* call synchronises it.  Calls on
+ *   one context must be serialised by the caller.
+ *
+ * Errors
+ *   Every call returns a bss_status; nothing throws or aborts across the ABI.
+ *   A numerical failure (non-finite or non-positive accepted ratio, or a wrap
+ *   drift above bss_options.drift_abort) poisons the context: the call that
+ *   detects it returns BSS_E_NUMERICAL and later calls return BSS_E_STATE.
+ *   Since sweeps are asynchronous, a failure inside a sweep is reported by
+ *   the next synchronising call.
+ */
+#ifndef BSSQMC_H
+#define BSSQMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BSS_OK = 0,
+  BSS_E_INVALID_ARG = 1,   /* argument out of range or inconsistent             */
+  BSS_E_UNSUPPORTED = 2,   /* valid physics this build does not run (odd L ...)  */
+  BSS_E_OUT_OF_MEMORY = 3, /* device allocation failed or workspace too small    */
+  BSS_E_DEVICE = 4,        /* HIP runtime error                                  */
+  BSS_E_NUMERICAL = 5,     /* non-finite / non-positive ratio, drift above limit */
+  BSS_E_STATE = 6          /* context poisoned, or call not valid in this state  */
+} bss_status;
+
+typedef enum {
+  BSS_PREC_FP64 = 0,  /* every step in FP64                                        */
+  BSS_PREC_MIXED = 1  /* FP32 G, flips, delayed updates and wraps (FP32 MFMA with
+                         FP32 accumulation); FP64 ratios, UDV/QR, recomputation    */
+} bss_precision;
+
+/* bss_options.flags */
+#define BSS_FLAG_RECORD_TRACE 0x1u /* record accept decisions (see bss_get_trace)     */
+#define BSS_FLAG_REPLAY_TRACE 0x2u /* take accept decisions from bss_set_trace        */
+#define BSS_FLAG_NO_GRAPH 0x4u     /* launch kernels directly instead of a hipGraph   */
+#define BSS_FLAG_PROFILE 0x8u      /* time every kernel launch with HIP events        */
+
+typedef struct {
+  uint32_t struct_size;  /* sizeof(bss_options)                                    */
+  int32_t precision;     /* bss_precision                                          */
+  int32_t delay_k;       /* delayed-update rank, 1..64; 0 = automatic              */
+  int32_t n_stab;        /* slices between FP64 recomputations; 0 = automatic      */
+  void *stream;          /* hipStream_t to run on; NULL = a library-owned stream   */
+  void *workspace;       /* optional device memory for all state (caller-owned)    */
+  size_t workspace_bytes;
+  uint32_t flags;        /* BSS_FLAG_*                                             */
+  double drift_abort;    /* poison the context if the wrap drift exceeds this;
+                            0 = never                                              */
+  int32_t trace_sweeps;  /* capacity of the record buffer, in sweeps               */
+} bss_options;
+
+/* One (L, U, t, beta, dtau) instance with its chains. */
+typedef struct {
+  int32_t L;
+  double U, t, beta, dtau;
+  uint64_t seed;         /* chain c uses Philox key (seed + c, instance index)     */
+  int32_t n_chains;
+} bss_instance;
+
+typedef struct {
+  int64_t sweeps;        /* completed sweeps                                       */
+  int64_t proposals;     /* summed over chains                                     */
+  int64_t accepted;
+  double drift_max;      /* max_ij |G_wrapped - G_fresh| over recomputations       */
+  double drift_mean;
+  double logw;           /* sum over chains of sum log R over accepted flips       */
+  int32_t sign;          /* product of sgn R over accepted flips (always +1 here)  */
+  int32_t n_chains;
+  int32_t N, Lambda, delay_k, n_stab;  /* resolved parameters                      */
+} bss_stats;
+
+/* Per-kernel launch timing collected under BSS_FLAG_PROFILE. */
+typedef struct {
+  char name[32];         /* kernel family: flip, wrap_gemm, gemm_f64, qr_udv, ... */
+  int64_t launches;
+  double total_ms;       /* summed HIP-event durations                             */
+} bss_kernel_time;
+
+/* Fill *opt with defaults (FP64, automatic k and n_stab, library stream). */
+void bss_options_default(bss_options *opt);
+
+typedef struct bss_ctx bss_ctx;  /* opaque, owned by the library */
+
+/* Create one instance (eq. (1)-(3) parameters; Lambda = beta/dtau must be an
+ * integer within 1e-9 relative).  INVALID_ARG: L < 2, U < 0, t < 0, beta <= 0,
+ * dtau <= 0, non-integral beta/dtau, n_chains < 1, bad options, out == NULL.
+ * UNSUPPORTED: odd L (periodic odd lattices are not bipartite, so the
+ * sign-free property does not hold) or N = L^2 > 512.  The field of chain c is
+ * drawn uniformly +-1 from the generator (counter (0, (l-1) N + i, 1, 0),
+ * +1 iff bit 63 of word 0 is clear) and G(tau = 0) is computed from scratch.
+ * opt may be NULL (defaults).  On success *out receives the context. */
+bss_status bss_create(int32_t L, double U, double t, double beta, double dtau, uint64_t seed,
+                      int32_t n_chains, const bss_options *opt, bss_ctx **out);
+
+/* Create a batch of n_inst instances sharing one context and one stream; an
+ * instance's index is its position in `inst` (it is the second Philox key
+ * word).  Same argument rules as bss_create for every instance. */
+bss_status bss_create_batch(const bss_instance *inst, int32_t n_inst, const bss_options *opt,
+                            bss_ctx **out);
+
+/* Device bytes a workspace must provide for this batch and these options. */
+bss_status bss_workspace_size(const bss_instance *inst, int32_t n_inst, const bss_options *opt,
+                              size_t *bytes);
+
+/* Run n_sweeps full sweeps of every chain of every instance (asynchronous).
+ * measure != 0: after each sweep accumulate double occupancy and G(tau_l, k)
+ * from the fresh G(tau = 0).  STATE if an instance is not at slice 1. */
+bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure);
+
+/* Advance every instance by n_slices slices (asynchronous); sweeps may end
+ * part-way.  Intended for slice-by-slice checks; no measurement. */
+bss_status bss_step_slices(bss_ctx *c, int32_t n_slices);
+
+/* Mean (and standard error, if stderr_out != NULL) of G(tau_l, k), paper sign,
+ * over all measured sweeps of instance `inst`: out[l * N + k], l = 0..Lambda.
+ * len must equal (Lambda + 1) * N.  The error is over chains (per-chain means)
+ * when there are >= 2 chains, else over 16..31 equal bins of one chain.
+ * STATE if nothing was measured. */
+bss_status bss_measure_gtau_k(bss_ctx *c, int32_t inst, double *mean, double *stderr_out,
+                              int64_t len);
+
+/* Mean (and standard error) of D = (1/N) sum_i <n_i,up n_i,dn>. */
+bss_status bss_measure_double_occ(bss_ctx *c, int32_t inst, double *mean, double *stderr_out);
+
+/* Discard accumulated measurements. */
+bss_status bss_reset_measurements(bss_ctx *c);
+
+/* Current equal-time Green function (positive convention) of one chain and
+ * spin (0 = up, 1 = down), FP64 row-major N x N, at the current slice
+ * position (start of the next slice to visit). */
+bss_status bss_get_green(bss_ctx *c, int32_t inst, int32_t chain, int32_t spin, double *out);
+
+/* Ising field of one chain, int8 [Lambda][N]. */
+bss_status bss_get_field(bss_ctx *c, int32_t inst, int32_t chain, int8_t *out);
+
+/* Replace the field of one chain (entries must be +-1, else INVALID_ARG).
+ * Requires every instance at slice 1; recomputes that chain's stabilisation
+ * data and G(tau = 0) from scratch. */
+bss_status bss_set_field(bss_ctx *c, int32_t inst, int32_t chain, const int8_t *in);
+
+/* Forced history (requires BSS_FLAG_REPLAY_TRACE): accept decisions for the
+ * next n_sweeps sweeps of instance `inst`, one byte per proposal (nonzero =
+ * accept), ordered [sweep][chain][l][i].  The decisions replace the
+ * Metropolis test; sweeping past the supplied history returns STATE. */
+bss_status bss_set_trace(bss_ctx *c, int32_t inst, const uint8_t *accept, int32_t n_sweeps);
+
+/* Recorded decisions (requires BSS_FLAG_RECORD_TRACE) of the first n_sweeps
+ * sweeps since creation, same layout as bss_set_trace. */
+bss_status bss_get_trace(bss_ctx *c, int32_t inst, uint8_t *accept, int32_t n_sweeps);
+
+/* Statistics of instance `inst` (acceptance, drift, log-weight, sign). */
+bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out);
+
+/* Checkpoint: with buf == NULL, *bytes receives the size needed; otherwise
+ * the fields, sweep counters and measurement accumulators are written to buf
+ * (*bytes in: capacity, out: size used).  bss_load restores them into a
+ * context created with the same instances and options and recomputes every
+ * G from its field, so a resumed run continues the same Markov chain. */
+bss_status bss_save(bss_ctx *c, void *buf, size_t *bytes);
+bss_status bss_load(bss_ctx *c, const void *buf, size_t bytes);
+
+/* Kernel timings since creation or the last bss_reset_profile (requires
+ * BSS_FLAG_PROFILE; synchronises).  Writes up to cap entries; *n_out
+ * receives the number of kernel families. */
+bss_status bss_get_profile(bss_ctx *c, bss_kernel_time *out, int32_t cap, int32_t *n_out);
+bss_status bss_reset_profile(bss_ctx *c);
+
+/* Release the context (NULL is allowed). */
+void bss_destroy(bss_ctx *c);
+
+const char *bss_status_string(bss_status s);
+/* Message of the last failed call on c (valid until the next call on c). */
+const char *bss_last_error(const bss_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,239 @@
+// Flip phase of one time slice: Metropolis decisions on the Ising field with
+// Sherman-Morrison updates of G delayed to rank k.
+//
+// One workgroup runs one Markov chain (both spins); thread j owns site j of
+// the slice.  Per proposal the determinant ratio is
+//   R = R_up R_dn,  R_sigma = 1 + (1 - G_sigma,jj) Delta_sigma,
+//   Delta_sigma = e^{-2 sigma lambda h_j} - 1,
+// and the flip is accepted iff u_j < R (u_j from Philox at counter
+// (sweep, (l-1) N + j, 0, 0)).  With the updates delayed,
+//   G = G0 - sum_m x_m y_m^T,
+// and thread j keeps its rows of X and Y and its current diagonal element
+// d_j = G_jj in registers.  Because every site's ratio depends only on its
+// own d_j, all sites are tested in parallel and a wavefront ballot picks the
+// first accepted site after the last one: the proposals rejected before it
+// are exactly those the sequential visit would reject.  On acceptance at
+// site i the new pair is
+//   c = G0 e_i - X (Y^T e_i),  r = e_i^T G0 - (e_i^T X) Y^T,
+//   x = (Delta/R)(e_i - c),    y = r,
+// and every d_j drops by x_j y_j.  When k pairs are stored (and at the end of
+// the slice) they are flushed into G0 by a rank-k MFMA product.
+#include "common.h"
+#include "kernels.h"
+
+namespace bss {
+
+namespace {
+
+constexpr int FB = 64;  // rows of X staged per flush block
+
+// G0 <- G0 - X Y^T for one spin.  X rows [i0, i0+FB) are staged into LDS by
+// their owners; Y^T columns come from the owners of the output columns.  The
+// block product runs on 16x16x4 MFMA tiles: wavefront w handles output
+// columns [16 w', 16 w' + 16) for w' = w, w + nw, ... of each row block.
+template <typename T, int KM>
+__device__ void flush_spin(T *G, int N, const T (&xs)[KM], const T (&ys)[KM], T *Xs, T *Ys) {
+  const int j = threadIdx.x, lane = j & 63, w = j >> 6, nw = blockDim.x >> 6;
+  const bool own = j < N;
+  // Y^T staged once: Ys[s][col]
+#pragma unroll
+  for (int s = 0; s < KM; ++s) Ys[s * (blockDim.x + 1) + j] = own ? ys[s] : (T)0;
+  typedef typename Mfma<T>::acc_t acc_t;
+  for (int i0 = 0; i0 < N; i0 += FB) {
+    __syncthreads();
+    if (j >= i0 && j < i0 + FB) {
+#pragma unroll
+      for (int s = 0; s < KM; ++s) Xs[(j - i0) * (KM + 1) + s] = own ? xs[s] : (T)0;
+    }
+    __syncthreads();
+    const int nrb = min(FB, N - i0);
+    // tiles: (row block of 16) x (column block of 16)
+    const int rtiles = (nrb + 15) >> 4, ctiles = (N + 15) >> 4;
+    for (int tile = w; tile < rtiles * ctiles; tile += nw) {
+      const int tr = tile / ctiles, tc = tile % ctiles;
+      acc_t acc = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int s0 = 0; s0 < KM; s0 += 4) {
+        const int s = s0 + (lane >> 4);
+        T a = (T)0, b = (T)0;
+        if (s < KM) {
+          a = Xs[(tr * 16 + (lane & 15)) * (KM + 1) + s];
+          b = Ys[s * (blockDim.x + 1) + tc * 16 + (lane & 15)];
+        }
+        acc = Mfma<T>::mac(a, b, acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + tr * 16 + Mfma<T>::row(lane, r);
+        const int col = tc * 16 + (lane & 15);
+        if (row < i0 + nrb && col < N) G[(long)row * N + col] -= acc[r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int KM, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
+  extern __shared__ char smem_raw[];
+  T *Xs = (T *)smem_raw;                                  // [FB][KM+1]
+  T *Ys = Xs + FB * (KM + 1);                             // [KM][blockDim+1]
+  __shared__ int first[16];
+  __shared__ T bX[2][KM], bY[2][KM];
+  __shared__ double bF[2];
+  __shared__ double s_logw;
+  __shared__ int s_acc, s_bad;
+
+  const int N = a.N, j = threadIdx.x, lane = j & 63, w = j >> 6, nw = blockDim.x >> 6;
+  const int c = blockIdx.x;
+  const bool own = j < N;
+  const long NN = (long)N * N;
+  T *G[2] = {(T *)a.G + (2L * c) * NN, (T *)a.G + (2L * c + 1) * NN};
+  int8_t *hl = a.h + ((long)c * a.Lam + (a.l - 1)) * N;
+  const int64_t sweep = *a.sweep;
+
+  int hj = own ? hl[j] : 1;
+  double uj = 2.0;
+  bool forced = false;
+  long trace_idx = -1;
+  if (own && a.trace_mode != 0) {
+    const int64_t rel = sweep - *a.trace_base;
+    if (rel >= 0 && rel < a.trace_sweeps)
+      trace_idx = ((rel * a.chains + c) * (long)a.Lam + (a.l - 1)) * N + j;
+  }
+  if (own) {
+    if (a.trace_mode == 2) {
+      if (trace_idx >= 0) forced = a.trace[trace_idx] != 0;
+      else atomicOr(a.err, 8);     // replay past the supplied history
+    } else {
+      uj = uniform53(philox_word0((uint64_t)sweep, (uint64_t)(a.l - 1) * N + j, 0, 0, a.seed + (uint64_t)c, a.inst));
+    }
+  }
+  T xs[2][KM], ys[2][KM];
+#pragma unroll
+  for (int s = 0; s < KM; ++s) { xs[0][s] = xs[1][s] = ys[0][s] = ys[1][s] = (T)0; }
+  double d[2];
+  d[0] = own ? (double)G[0][(long)j * N + j] : 0.0;
+  d[1] = own ? (double)G[1][(long)j * N + j] : 0.0;
+  bool mine = false;   // my site was accepted
+  if (j == 0) { s_logw = 0.0; s_acc = 0; s_bad = 0; }
+  __syncthreads();
+
+  int m = 0, pos = 0;
+  for (;;) {
+    bool acc = false;
+    if (own && j >= pos) {
+      const double du = hj > 0 ? a.dlt_up_p : a.dlt_up_m;
+      const double dd = hj > 0 ? a.dlt_dn_p : a.dlt_dn_m;
+      const double R = (1.0 + (1.0 - d[0]) * du) * (1.0 + (1.0 - d[1]) * dd);
+      acc = (a.trace_mode == 2) ? forced : (uj < R);
+    }
+    const unsigned long long bal = __ballot(acc);
+    if (lane == 0) first[w] = bal ? (w * 64 + __ffsll((long long)bal) - 1) : 0x7fffffff;
+    __syncthreads();
+    int ist = 0x7fffffff;
+    for (int q = 0; q < nw; ++q) ist = min(ist, first[q]);
+    if (ist >= N) break;
+    if (j == ist) {
+      const double du = hj > 0 ? a.dlt_up_p : a.dlt_up_m;
+      const double dd = hj > 0 ? a.dlt_dn_p : a.dlt_dn_m;
+      const double Ru = 1.0 + (1.0 - d[0]) * du, Rd = 1.0 + (1.0 - d[1]) * dd;
+      const double R = Ru * Rd;
+      bF[0] = du / Ru;
+      bF[1] = dd / Rd;
+#pragma unroll
+      for (int s = 0; s < KM; ++s) { bX[0][s] = xs[0][s]; bY[0][s] = ys[0][s]; bX[1][s] = xs[1][s]; bY[1][s] = ys[1][s]; }
+      if (!(R > 0.0) || !isfinite(R)) s_bad = 1;
+      s_logw += log(R);
+      s_acc += 1;
+      hj = -hj;
+      hl[j] = (int8_t)hj;
+      mine = true;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      T gr = 0, gc = 0;
+      if (own) {
+        gr = G[sp][(long)ist * N + j];
+        gc = G[sp][(long)j * N + ist];
+      }
+      T cv = gc, rv = gr;
+#pragma unroll
+      for (int s = 0; s < KM; ++s) {
+        cv -= xs[sp][s] * bY[sp][s];
+        rv -= bX[sp][s] * ys[sp][s];
+      }
+      const T xn = (T)bF[sp] * ((j == ist ? (T)1 : (T)0) - cv);
+      const T yn = own ? rv : (T)0;
+      const T xv = own ? xn : (T)0;
+#pragma unroll
+      for (int s = 0; s < KM; ++s)
+        if (s == m) { xs[sp][s] = xv; ys[sp][s] = yn; }
+      d[sp] -= (double)xv * (double)yn;
+    }
+    ++m;
+    pos = ist + 1;
+    if (m == a.k) {
+      flush_spin<T, KM>(G[0], N, xs[0], ys[0], Xs, Ys);
+      flush_spin<T, KM>(G[1], N, xs[1], ys[1], Xs, Ys);
+#pragma unroll
+      for (int s = 0; s < KM; ++s) { xs[0][s] = xs[1][s] = ys[0][s] = ys[1][s] = (T)0; }
+      d[0] = own ? (double)G[0][(long)j * N + j] : 0.0;
+      d[1] = own ? (double)G[1][(long)j * N + j] : 0.0;
+      m = 0;
+    }
+    __syncthreads();
+  }
+  if (m > 0) {
+    flush_spin<T, KM>(G[0], N, xs[0], ys[0], Xs, Ys);
+    flush_spin<T, KM>(G[1], N, xs[1], ys[1], Xs, Ys);
+  }
+  // diagonal factors of the updated slice for the wrap: D = e^{sigma lambda h}
+  if (own) {
+    T *dv0 = (T *)a.dv + (2L * c) * 2 * N;
+    T *dv1 = dv0 + 2 * N;
+    const T up = hj > 0 ? (T)a.elam : (T)a.emlam;
+    const T dn = hj > 0 ? (T)a.emlam : (T)a.elam;
+    dv0[j] = up; dv0[N + j] = dn;      // spin up: D, D^{-1}
+    dv1[j] = dn; dv1[N + j] = up;      // spin down
+    if (a.trace_mode == 1 && trace_idx >= 0) a.trace[trace_idx] = mine ? 1 : 0;
+  }
+  __syncthreads();
+  if (j == 0) {
+    ChainStats *st = a.stats + c;
+    st->proposals += N;
+    st->accepted += s_acc;
+    st->logw += s_logw;
+    if (s_bad) atomicOr(a.err, 1);
+  }
+}
+
+template <typename T, int KM>
+hipError_t launch_k(const FlipArgs &a, hipStream_t s) {
+  const int threads = ((a.N + 63) / 64) * 64;
+  const size_t lds = sizeof(T) * ((size_t)FB * (KM + 1) + (size_t)KM * (threads + 1));
+  if (threads <= 256)
+    hipLaunchKernelGGL((k_flip<T, KM, 256>), dim3(a.chains), dim3(threads), lds, s, a);
+  else if (threads <= 512)
+    hipLaunchKernelGGL((k_flip<T, KM, 512>), dim3(a.chains), dim3(threads), lds, s, a);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_t(const FlipArgs &a, hipStream_t s) {
+  if (a.k <= 1) return launch_k<T, 1>(a, s);
+  if (a.k <= 8) return launch_k<T, 8>(a, s);
+  if (a.k <= 16) return launch_k<T, 16>(a, s);
+  if (a.k <= 32) return launch_k<T, 32>(a, s);
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t flip_slice(const FlipArgs &a, bool fp64, hipStream_t s) {
+  return fp64 ? launch_t<double>(a, s) : launch_t<float>(a, s);
+}
+
+}  // namespace bss

@@ -1,0 +1,113 @@
+// Measurement kernels (FP64): double occupancy and the momentum-resolved
+// time-displaced Green function, accumulated per chain in blocked bins.
+//
+//   D = (1/N) sum_i (1 - G_up,ii)(1 - G_dn,ii)        (Wick, spins decouple per field)
+//   G(tau_l, k) = -1/2 sum_sigma (1/N) sum_ij cos(k.(r_i - r_j)) G_sigma,ij(tau_l, 0)
+// The second is evaluated through the lattice-averaged g(delta) =
+// (1/N) sum_i G_{i+delta, i}, then G(tau_l, k) = -1/2 sum_sigma sum_delta cos(k.delta) g(delta).
+#include "common.h"
+#include "kernels.h"
+#include "measure.h"
+
+namespace bss {
+
+namespace {
+
+// Start a measurement: pick the bin of measurement n = count[c]; when all
+// nbins bins are full, merge neighbours pairwise and double the bin size.
+__global__ void k_meas_begin(MeasState ms, int chains) {
+  const int c = blockIdx.x;
+  if (c >= chains) return;
+  int64_t n = ms.count[c];
+  int64_t bs = ms.binsize[c];
+  __shared__ int merge;
+  if (threadIdx.x == 0) merge = (n / bs) >= ms.nbins;
+  __syncthreads();
+  if (merge) {
+    const long per_g = ms.glen;
+    double *gb = ms.gk + (long)c * ms.nbins_g * per_g;
+    double *db = ms.docc + (long)c * ms.nbins;
+    if (ms.nbins_g == ms.nbins) {
+      // per offset, sequentially in the bin index: bin b is read (as 2b' or
+      // 2b'+1 for b' = b/2 < b) before it is overwritten
+      for (long off = threadIdx.x; off < per_g; off += blockDim.x) {
+        for (int bin = 0; bin < ms.nbins / 2; ++bin)
+          gb[bin * per_g + off] = gb[(2 * bin) * per_g + off] + gb[(2 * bin + 1) * per_g + off];
+        for (int bin = ms.nbins / 2; bin < ms.nbins; ++bin) gb[bin * per_g + off] = 0.0;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int b = 0; b < ms.nbins / 2; ++b) db[b] = db[2 * b] + db[2 * b + 1];
+      for (int b = ms.nbins / 2; b < ms.nbins; ++b) db[b] = 0.0;
+      ms.binsize[c] = bs * 2;
+    }
+    bs *= 2;
+  }
+  if (threadIdx.x == 0) ms.cur[c] = (int)(n / bs);
+}
+
+__global__ void k_meas_end(MeasState ms, int chains) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < chains) ms.count[c] += 1;
+}
+
+__global__ __launch_bounds__(256) void k_meas_docc(MeasState ms, const double *Gf, int N) {
+  __shared__ double red[16];
+  const int c = blockIdx.x;
+  const double *gu = Gf + (2L * c) * N * N, *gd = gu + (long)N * N;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x)
+    s += (1.0 - gu[(long)i * N + i]) * (1.0 - gd[(long)i * N + i]);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) ms.docc[(long)c * ms.nbins + ms.cur[c]] += s / N;
+}
+
+// One chain per block: g_sigma(delta) summed over spins, then the cosine
+// transform, added to the slice-l row of the chain's current bin.
+__global__ __launch_bounds__(256) void k_meas_gk(MeasState ms, const double *Gt, int L, int l) {
+  extern __shared__ double gd[];   // [N] g(delta) summed over spins
+  const int N = L * L, c = blockIdx.x;
+  const double *g0 = Gt + (2L * c) * N * N, *g1 = g0 + (long)N * N;
+  for (int dlt = threadIdx.x; dlt < N; dlt += blockDim.x) {
+    const int dx = dlt % L, dy = dlt / L;
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const int xi = i % L, yi = i / L;
+      const int r = ((xi + dx) % L) + L * ((yi + dy) % L);
+      s += g0[(long)r * N + i] + g1[(long)r * N + i];
+    }
+    gd[dlt] = s / N;
+  }
+  __syncthreads();
+  double *out = ms.gk + ((long)c * ms.nbins_g + (ms.nbins_g == 1 ? 0 : ms.cur[c])) * ms.glen + (long)l * N;
+  for (int k = threadIdx.x; k < N; k += blockDim.x) {
+    const int mx = k % L, my = k / L;
+    double s = 0.0;
+    for (int dlt = 0; dlt < N; ++dlt) {
+      const int ph = (mx * (dlt % L) + my * (dlt / L)) % L;
+      s += cospi(2.0 * ph / L) * gd[dlt];
+    }
+    out[k] += -0.5 * s;
+  }
+}
+}  // namespace
+
+hipError_t meas_begin(const MeasState &ms, int chains, hipStream_t s) {
+  hipLaunchKernelGGL(k_meas_begin, dim3(chains), dim3(256), 0, s, ms, chains);
+  return hipGetLastError();
+}
+hipError_t meas_end(const MeasState &ms, int chains, hipStream_t s) {
+  hipLaunchKernelGGL(k_meas_end, dim3((chains + 255) / 256), dim3(256), 0, s, ms, chains);
+  return hipGetLastError();
+}
+hipError_t meas_docc(const MeasState &ms, const double *Gf, int chains, int N, hipStream_t s) {
+  hipLaunchKernelGGL(k_meas_docc, dim3(chains), dim3(256), 0, s, ms, Gf, N);
+  return hipGetLastError();
+}
+hipError_t meas_gk(const MeasState &ms, const double *Gt, int chains, int L, int l, hipStream_t s) {
+  hipLaunchKernelGGL(k_meas_gk, dim3(chains), dim3(256), sizeof(double) * L * L, s, ms, Gt, L, l);
+  return hipGetLastError();
+}
+
+}  // namespace bss

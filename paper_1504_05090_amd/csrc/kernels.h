@@ -1,0 +1,87 @@
+// Host-side launch interface of the gfx950 kernels (internal to the library).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bss {
+
+// Batched C = alpha * diag(rs) * op(A) diag(ks) op(B) * diag(cs) + beta * C.
+// Strides are in elements; a stride of 0 shares one matrix/vector across the batch.
+struct GemmDesc {
+  int M, N, K, batch;
+  const void *A; long lda, sA;
+  const void *B; long ldb, sB;
+  void *C; long ldc, sC;
+  const void *ks; long sks;   // length-K scale of A's columns (nullable)
+  const void *rs; long srs;   // length-M scale of the result rows (nullable)
+  const void *cs; long scs;   // length-N scale of the result columns (nullable)
+  double alpha, beta;
+};
+hipError_t gemm_f64(const GemmDesc &d, bool ta, bool tb, hipStream_t s);
+hipError_t gemm_f32(const GemmDesc &d, bool ta, bool tb, hipStream_t s);
+
+// Per-chain device statistics.
+struct ChainStats {
+  int64_t proposals, accepted;
+  double logw;
+  double drift_max, drift_sum;
+  int64_t drift_count;
+  int32_t sign, pad;
+};
+
+// Flip phase of one slice for every chain of one instance.
+struct FlipArgs {
+  int N, Lam, l, k, chains;
+  void *G;              // [2*chains][N][N] bulk type
+  int8_t *h;            // [chains][Lam][N]
+  void *dv;             // out: [2*chains][2][N] bulk type: D_l and D_l^{-1}
+  double dlt_up_p, dlt_up_m;   // Delta_up for h = +1 / -1
+  double dlt_dn_p, dlt_dn_m;   // Delta_dn for h = +1 / -1
+  double elam, emlam;          // e^{lambda}, e^{-lambda}
+  uint64_t seed, inst;
+  const int64_t *sweep;        // device sweep counter
+  int trace_mode;              // 0 none, 1 record, 2 replay
+  uint8_t *trace;              // [sweeps][chains][Lam][N]
+  const int64_t *trace_base;   // sweep index of trace entry 0
+  int64_t trace_sweeps;        // capacity in sweeps
+  ChainStats *stats;
+  int *err;
+};
+hipError_t flip_slice(const FlipArgs &a, bool fp64, hipStream_t s);
+
+// setup
+hipError_t build_exp(int L, double t, double dtau, double *Em, double *Ep, void *Et_m, void *Et_p,
+                     bool fp64, hipStream_t s);
+hipError_t init_field(int8_t *h, int chains, int Lam, int N, uint64_t seed, uint64_t inst,
+                      hipStream_t s);
+// out[mat][q - lo][i] = exp(sigma lambda h[chain][q-1][i]), q = lo..hi (FP64)
+hipError_t slice_scales(const int8_t *h, int chains, int Lam, int N, int lo, int hi, double elam,
+                        double emlam, double *out, hipStream_t s);
+// P[mat] = E * diag(d[mat])
+hipError_t scale_columns(const double *E, const double *d, long sd, double *P, int mats, int N,
+                         hipStream_t s);
+hipError_t set_identity_udv(double *U, double *D, double *V, int mats, int N, hipStream_t s);
+hipError_t copy_to_bulk(const double *src, void *dst, long n, bool fp64, hipStream_t s);
+hipError_t bump_counter(int64_t *ctr, hipStream_t s);
+
+// FP64 stabilisation
+// Pre-pivoted Householder QR of X (overwritten): U = Q, D = diag(R),
+// RP = D^{-1} R Pi^T (so that X = U diag(D) RP).
+hipError_t qr_udv(double *X, double *U, double *D, double *RP, int mats, int N, hipStream_t s);
+// M Z = B by Householder QR (M overwritten, B replaced by Z).
+hipError_t qr_solve(double *M, double *B, int mats, int N, hipStream_t s);
+// Middle matrix of the two-sided fresh-G formula and its right-hand side.
+hipError_t fresh_prep(const double *UR, const double *DR, const double *VR, double *W1,
+                      const double *W2, const double *DL, double *RHS, int mats, int N,
+                      hipStream_t s);
+// drift = max |G - Gf| per chain; G <- Gf (bulk rounding)
+hipError_t drift_replace(void *G, const double *Gf, int chains, int N, bool fp64,
+                         ChainStats *stats, int *err, double drift_abort, bool count,
+                         hipStream_t s);
+// RHS = Ds_R V_R (right-hand side of the time-displaced G(tau_l, 0) system)
+hipError_t time_rhs(const double *DR, const double *VR, double *RHS, int mats, int N, hipStream_t s);
+// reciprocal of the big parts of D (for the final left product)
+hipError_t inv_big(const double *D, double *out, long n, hipStream_t s);
+
+}  // namespace bss

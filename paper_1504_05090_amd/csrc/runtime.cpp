@@ -1,0 +1,975 @@
+// Host runtime of the BSS-QMC sweep library: argument checking, device
+// memory layout, the per-slice launch schedule, stabilisation bookkeeping,
+// measurement, trace record/replay, checkpoints and the C ABI of bssqmc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bssqmc.h"
+#include "kernels.h"
+#include "measure.h"
+
+using namespace bss;
+
+namespace {
+
+constexpr int NBINS = 32;
+constexpr int NMAX = 512;
+
+// ---------------------------------------------------------------------------
+// device memory carving: one region (library- or caller-owned), 256-byte
+// aligned sub-buffers
+struct Carver {
+  char *base = nullptr;
+  size_t off = 0;
+  template <typename T> T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += sizeof(T) * count;
+    return p;
+  }
+};
+
+struct Inst {
+  // parameters
+  int L = 0, N = 0, Lam = 0, C = 0, mats = 0, k = 1, n_stab = 1, nb = 1, index = 0;
+  double U = 0, t = 0, beta = 0, dtau = 0, lambda = 0;
+  uint64_t seed = 0;
+  // device state (bulk = FP32 in mixed mode, FP64 otherwise)
+  double *Em = nullptr, *Ep = nullptr;   // e^{-dtau K}, e^{+dtau K}
+  void *Etm = nullptr, *Etp = nullptr;   // bulk copies
+  void *G = nullptr, *Tw = nullptr, *dv = nullptr;
+  int8_t *h = nullptr;
+  double *dvD = nullptr;                 // [mats][n_stab][N]
+  double *Pc = nullptr, *Pw = nullptr;   // block products [nb][mats][N^2]
+  double *RU = nullptr, *RD = nullptr, *RV = nullptr;   // right chain after block b: [nb][...]
+  double *LU = nullptr, *LD = nullptr, *LV = nullptr;   // left factors, entry b: (B_Lam..B_{l_b+1})^T
+  double *W1 = nullptr, *W2 = nullptr, *W3 = nullptr, *Gf = nullptr, *Gt = nullptr, *invb = nullptr;
+  ChainStats *stats = nullptr;
+  int64_t *sweep_ctr = nullptr, *trace_base = nullptr;
+  uint8_t *trace = nullptr;
+  int64_t trace_alloc = 0;               // sweeps the trace buffer holds
+  int64_t trace_cap = 0;                 // sweeps of the current history window
+  MeasState ms{};
+  // host
+  int slice = 1;
+  int64_t sweeps = 0;
+  int64_t trace_host_base = 0;
+};
+
+size_t nn(const Inst &I) { return (size_t)I.N * I.N; }
+
+}  // namespace
+
+struct bss_ctx {
+  std::vector<Inst> inst;
+  bss_options opt{};
+  bool fp64 = true;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  char *mem = nullptr;
+  size_t mem_bytes = 0;
+  bool own_mem = false;
+  int *err = nullptr;
+  bool poisoned = false;
+  std::string last_error;
+  int device = 0;
+  // BSS_FLAG_PROFILE: event pairs per kernel family, resolved on demand
+  bool profile = false;
+  struct Fam {
+    const char *name;
+    int64_t launches = 0;
+    double ms = 0.0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  };
+  std::vector<Fam> fam;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+enum KFam { F_FLIP, F_WRAP, F_GEMM64, F_QR_UDV, F_QR_SOLVE, F_ELEM, F_DRIFT, F_MEAS, F_COUNT };
+const char *const FAM_NAMES[F_COUNT] = {"flip", "wrap_gemm", "gemm_f64", "qr_udv", "qr_solve", "elementwise",
+                                        "drift_replace", "measure"};
+
+hipEvent_t take_event(bss_ctx *c) {
+  if (!c->pool.empty()) { hipEvent_t e = c->pool.back(); c->pool.pop_back(); return e; }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// brackets the launches issued in its lifetime with a pair of events
+struct Timed {
+  bss_ctx *c;
+  int fam;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Timed(bss_ctx *c_, int f, hipStream_t s_) : c(c_), fam(f), s(s_) {
+    if (c->profile && (a = take_event(c))) hipEventRecord(a, s);
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) { c->pool.push_back(a); return; }
+    hipEventRecord(b, s);
+    c->fam[fam].pending.push_back({a, b});
+  }
+};
+}  // namespace
+
+namespace {
+
+bss_status fail(bss_ctx *c, bss_status s, const std::string &msg) {
+  if (c) c->last_error = msg;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(ctx, BSS_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool valid_instance(const bss_instance &in, std::string &why, bss_status &code) {
+  code = BSS_E_INVALID_ARG;
+  if (in.L < 2) { why = "L must be >= 2"; return false; }
+  if (!(in.U >= 0.0) || !std::isfinite(in.U)) { why = "U must be finite and >= 0"; return false; }
+  if (!(in.t >= 0.0) || !std::isfinite(in.t)) { why = "t must be finite and >= 0"; return false; }
+  if (!(in.beta > 0.0) || !std::isfinite(in.beta)) { why = "beta must be > 0"; return false; }
+  if (!(in.dtau > 0.0) || !std::isfinite(in.dtau)) { why = "dtau must be > 0"; return false; }
+  const double r = in.beta / in.dtau;
+  const double lam = std::round(r);
+  if (lam < 1 || std::fabs(r - lam) > 1e-9 * r) { why = "beta/dtau must be an integer"; return false; }
+  if (in.n_chains < 1) { why = "n_chains must be >= 1"; return false; }
+  if (in.n_chains > 32767) { why = "n_chains must be <= 32767"; return false; }
+  code = BSS_E_UNSUPPORTED;
+  if (in.L % 2) { why = "odd L is not supported (periodic odd lattices are not bipartite)"; return false; }
+  if ((long)in.L * in.L > NMAX) { why = "N = L^2 > 512 is not supported"; return false; }
+  return true;
+}
+
+// automatic delay depth and stabilisation interval
+int auto_k(int N) { return N <= 16 ? 1 : (N <= 64 ? 16 : 32); }
+int auto_nstab(double U, double dtau) {
+  // keep the plain FP64 block product of n slices well conditioned:
+  // cond(B) ~ e^{2 lambda + 8 t dtau}; aim at a product condition of ~1e8
+  const double lam = std::acosh(std::exp(0.5 * dtau * U));
+  const double per = 2.0 * lam + 2.0 * dtau;  // log cond of one slice, t = 0.25
+  int n = (int)std::floor(std::log(1e8) / std::max(per, 1e-3));
+  return std::max(1, std::min(n, 10));
+}
+
+void layout(Inst &I, bool fp64, Carver &cv, int64_t trace_sweeps, bool tracing) {
+  const size_t NN = nn(I), M = (size_t)I.mats, bsz = fp64 ? 8 : 4;
+  I.Em = cv.take<double>(NN);
+  I.Ep = cv.take<double>(NN);
+  if (!fp64) { I.Etm = cv.take<char>(NN * bsz); I.Etp = cv.take<char>(NN * bsz); }
+  else { I.Etm = I.Em; I.Etp = I.Ep; }
+  I.G = cv.take<char>(M * NN * bsz);
+  I.Tw = cv.take<char>(M * NN * bsz);
+  I.dv = cv.take<char>(M * 2 * I.N * bsz);
+  I.h = cv.take<int8_t>((size_t)I.C * I.Lam * I.N);
+  I.dvD = cv.take<double>(M * I.n_stab * I.N);
+  I.Pc = cv.take<double>((size_t)I.nb * M * NN);
+  I.Pw = cv.take<double>(M * NN);
+  I.RU = cv.take<double>((size_t)I.nb * M * NN);
+  I.RD = cv.take<double>((size_t)I.nb * M * I.N);
+  I.RV = cv.take<double>((size_t)I.nb * M * NN);
+  I.LU = cv.take<double>((size_t)I.nb * M * NN);
+  I.LD = cv.take<double>((size_t)I.nb * M * I.N);
+  I.LV = cv.take<double>((size_t)I.nb * M * NN);
+  I.W1 = cv.take<double>(M * NN);
+  I.W2 = cv.take<double>(M * NN);
+  I.W3 = cv.take<double>(M * NN);
+  I.Gf = cv.take<double>(M * NN);
+  I.Gt = cv.take<double>(M * NN);
+  I.invb = cv.take<double>(M * I.N);
+  I.stats = cv.take<ChainStats>(I.C);
+  I.sweep_ctr = cv.take<int64_t>(1);
+  I.trace_base = cv.take<int64_t>(1);
+  I.trace_alloc = I.trace_cap = tracing ? trace_sweeps : 0;
+  I.trace = cv.take<uint8_t>(tracing ? (size_t)trace_sweeps * I.C * I.Lam * I.N : 1);
+  I.ms.nbins = NBINS;
+  I.ms.nbins_g = I.C == 1 ? NBINS : 1;
+  I.ms.glen = (long)(I.Lam + 1) * I.N;
+  I.ms.docc = cv.take<double>((size_t)I.C * NBINS);
+  I.ms.gk = cv.take<double>((size_t)I.C * I.ms.nbins_g * I.ms.glen);
+  I.ms.count = cv.take<int64_t>(I.C);
+  I.ms.binsize = cv.take<int64_t>(I.C);
+  I.ms.cur = cv.take<int>(I.C);
+}
+
+bool resolve(const bss_instance *in, int n, const bss_options &opt, std::vector<Inst> &out,
+             std::string &why, bss_status &code) {
+  out.clear();
+  for (int i = 0; i < n; ++i) {
+    if (!valid_instance(in[i], why, code)) { why = "instance " + std::to_string(i) + ": " + why; return false; }
+    Inst I;
+    I.L = in[i].L; I.N = I.L * I.L; I.U = in[i].U; I.t = in[i].t; I.beta = in[i].beta; I.dtau = in[i].dtau;
+    I.Lam = (int)std::lround(I.beta / I.dtau);
+    I.C = in[i].n_chains; I.mats = 2 * I.C; I.seed = in[i].seed; I.index = i;
+    I.lambda = std::acosh(std::exp(0.5 * I.dtau * I.U));
+    I.k = opt.delay_k > 0 ? opt.delay_k : auto_k(I.N);
+    I.n_stab = opt.n_stab > 0 ? opt.n_stab : auto_nstab(I.U, I.dtau);
+    I.n_stab = std::min(I.n_stab, I.Lam);
+    I.nb = (I.Lam + I.n_stab - 1) / I.n_stab;
+    out.push_back(I);
+  }
+  return true;
+}
+
+bool check_options(const bss_options *o, std::string &why) {
+  if (!o) return true;
+  if (o->struct_size != sizeof(bss_options)) { why = "bss_options.struct_size mismatch"; return false; }
+  if (o->precision != BSS_PREC_FP64 && o->precision != BSS_PREC_MIXED) { why = "bad precision"; return false; }
+  if (o->delay_k < 0 || o->delay_k > 32) { why = "delay_k must be in 0..32"; return false; }
+  if (o->n_stab < 0) { why = "n_stab must be >= 0"; return false; }
+  if ((o->flags & BSS_FLAG_RECORD_TRACE) && (o->flags & BSS_FLAG_REPLAY_TRACE)) { why = "record and replay are exclusive"; return false; }
+  if ((o->flags & BSS_FLAG_RECORD_TRACE) && o->trace_sweeps < 1) { why = "trace_sweeps must be >= 1 to record"; return false; }
+  if (o->trace_sweeps < 0) { why = "trace_sweeps must be >= 0"; return false; }
+  if (!(o->drift_abort >= 0.0)) { why = "drift_abort must be >= 0"; return false; }
+  return true;
+}
+
+size_t total_bytes(std::vector<Inst> &v, const bss_options &opt) {
+  Carver cv;
+  const bool tracing = (opt.flags & (BSS_FLAG_RECORD_TRACE | BSS_FLAG_REPLAY_TRACE)) != 0;
+  for (auto &I : v) layout(I, opt.precision == BSS_PREC_FP64, cv, std::max(opt.trace_sweeps, 1), tracing);
+  return cv.off + 256;
+}
+
+// ---------------------------------------------------------------------------
+// launch schedule
+
+GemmDesc gemm_desc(int N, int batch) {
+  GemmDesc d{};
+  d.M = d.N = d.K = N;
+  d.batch = batch;
+  d.lda = d.ldb = d.ldc = N;
+  d.alpha = 1.0;
+  d.beta = 0.0;
+  return d;
+}
+
+struct Exec {
+  bss_ctx *c;
+  Inst &I;
+  hipStream_t s;
+  hipError_t e = hipSuccess;
+  void chk(hipError_t x) { if (e == hipSuccess && x != hipSuccess) e = x; }
+
+  size_t NN() const { return nn(I); }
+  double *Pc(int b) const { return I.Pc + (size_t)b * I.mats * NN(); }
+  double *RU(int b) const { return I.RU + (size_t)b * I.mats * NN(); }
+  double *RD(int b) const { return I.RD + (size_t)b * I.mats * I.N; }
+  double *RV(int b) const { return I.RV + (size_t)b * I.mats * NN(); }
+  double *LU(int b) const { return I.LU + (size_t)b * I.mats * NN(); }
+  double *LD(int b) const { return I.LD + (size_t)b * I.mats * I.N; }
+  double *LV(int b) const { return I.LV + (size_t)b * I.mats * NN(); }
+
+  void gemm64(const double *A, bool ta, const double *B, bool tb, double *C, long sA, long sB,
+              const double *ks = nullptr, long sks = 0, const double *cs = nullptr, long scs = 0) {
+    GemmDesc d = gemm_desc(I.N, I.mats);
+    d.A = A; d.sA = sA; d.B = B; d.sB = sB; d.C = C; d.sC = (long)NN();
+    d.ks = ks; d.sks = sks; d.cs = cs; d.scs = scs;
+    Timed tm(c, F_GEMM64, s);
+    chk(gemm_f64(d, ta, tb, s));
+  }
+
+  // P_b = B_hi ... B_lo (FP64) into Pc(b)
+  void block_product(int b) {
+    const int lo = b * I.n_stab + 1, hi = std::min((b + 1) * I.n_stab, I.Lam), nq = hi - lo + 1;
+    double *bufs[2] = {Pc(b), I.Pw};
+    int cur = (nq % 2 == 1) ? 0 : 1;     // so that the last product lands in Pc(b)
+    {
+      Timed tm(c, F_ELEM, s);
+      chk(slice_scales(I.h, I.C, I.Lam, I.N, lo, hi, std::exp(I.lambda), std::exp(-I.lambda), I.dvD, s));
+      chk(scale_columns(I.Em, I.dvD, (long)nq * I.N, bufs[cur], I.mats, I.N, s));
+    }
+    for (int q = 1; q < nq; ++q) {
+      gemm64(I.Em, false, bufs[cur], false, bufs[cur ^ 1], 0, (long)NN(), I.dvD + (size_t)q * I.N,
+             (long)nq * I.N);
+      cur ^= 1;
+    }
+  }
+
+  // (U,D,V)_out = UDV of op(A) (U D V)_in
+  void udv_update(const double *A, bool ta, const double *Ui, const double *Di, const double *Vi, double *Uo,
+                  double *Do, double *Vo) {
+    gemm64(A, ta, Ui, false, I.W1, (long)NN(), (long)NN(), nullptr, 0, Di, I.N);
+    {
+      Timed tm(c, F_QR_UDV, s);
+      chk(qr_udv(I.W1, Uo, Do, I.W2, I.mats, I.N, s));
+    }
+    gemm64(I.W2, false, Vi, false, Vo, (long)NN(), (long)NN());
+  }
+
+  // G = (I + R L)^{-1} from the right chain after block b and left entry b
+  // (none for the last block), into Gf.  With rhs_v the right-hand side is
+  // Ds_R V_R instead, which yields G(tau_{l_b}, 0) (time-displaced).
+  void fresh(int b, bool rhs_v, double *out) {
+    const bool left = b < I.nb - 1;
+    if (left) {
+      gemm64(RU(b), true, LU(b), false, I.W1, (long)NN(), (long)NN());
+      gemm64(RV(b), false, LV(b), true, I.W2, (long)NN(), (long)NN());
+      Timed tm(c, F_ELEM, s);
+      chk(fresh_prep(RU(b), RD(b), RV(b), I.W1, I.W2, LD(b), I.W3, I.mats, I.N, s));
+    } else {
+      Timed tm(c, F_ELEM, s);
+      chk(fresh_prep(RU(b), RD(b), RV(b), I.W1, nullptr, nullptr, I.W3, I.mats, I.N, s));
+    }
+    if (rhs_v) { Timed tm(c, F_ELEM, s); chk(time_rhs(RD(b), RV(b), I.W3, I.mats, I.N, s)); }
+    { Timed tm(c, F_QR_SOLVE, s); chk(qr_solve(I.W1, I.W3, I.mats, I.N, s)); }
+    if (left) {
+      { Timed tm(c, F_ELEM, s); chk(inv_big(LD(b), I.invb, (long)I.mats * I.N, s)); }
+      gemm64(LU(b), false, I.W3, false, out, (long)NN(), (long)NN(), I.invb, I.N);
+    } else {
+      chk(hipMemcpyAsync(out, I.W3, sizeof(double) * I.mats * NN(), hipMemcpyDeviceToDevice, s));
+    }
+  }
+
+  void right_update(int b) {
+    if (b == 0) {
+      chk(set_identity_udv(I.W3, I.invb, I.Gt, I.mats, I.N, s));   // identity U, D, V scratch
+      udv_update(Pc(0), false, I.W3, I.invb, I.Gt, RU(0), RD(0), RV(0));
+    } else {
+      udv_update(Pc(b), false, RU(b - 1), RD(b - 1), RV(b - 1), RU(b), RD(b), RV(b));
+    }
+  }
+
+  void left_rebuild() {
+    const int last = I.nb - 1;
+    chk(set_identity_udv(LU(last), LD(last), LV(last), I.mats, I.N, s));
+    for (int b = last - 1; b >= 0; --b) udv_update(Pc(b + 1), true, LU(b + 1), LD(b + 1), LV(b + 1), LU(b), LD(b), LV(b));
+  }
+
+  // full recomputation from the current field (creation, set_field, load)
+  void initialise(bool draw_field) {
+    if (draw_field) chk(init_field(I.h, I.C, I.Lam, I.N, I.seed, (uint64_t)I.index, s));
+    for (int b = 0; b < I.nb; ++b) {
+      block_product(b);
+      right_update(b);
+    }
+    fresh(I.nb - 1, false, I.Gf);
+    chk(drift_replace(I.G, I.Gf, I.C, I.N, c->fp64, I.stats, c->err, 0.0, false, s));
+    left_rebuild();
+  }
+
+  void flip(int l) {
+    FlipArgs a{};
+    a.N = I.N; a.Lam = I.Lam; a.l = l; a.k = I.k; a.chains = I.C;
+    a.G = I.G; a.h = I.h; a.dv = I.dv;
+    a.dlt_up_p = std::exp(-2.0 * I.lambda) - 1.0;   // sigma = +1, h = +1
+    a.dlt_up_m = std::exp(2.0 * I.lambda) - 1.0;    // sigma = +1, h = -1
+    a.dlt_dn_p = std::exp(2.0 * I.lambda) - 1.0;    // sigma = -1, h = +1
+    a.dlt_dn_m = std::exp(-2.0 * I.lambda) - 1.0;   // sigma = -1, h = -1
+    a.elam = std::exp(I.lambda); a.emlam = std::exp(-I.lambda);
+    a.seed = I.seed; a.inst = (uint64_t)I.index;
+    a.sweep = I.sweep_ctr;
+    a.trace_mode = (c->opt.flags & BSS_FLAG_RECORD_TRACE) ? 1 : ((c->opt.flags & BSS_FLAG_REPLAY_TRACE) ? 2 : 0);
+    a.trace = I.trace; a.trace_base = I.trace_base; a.trace_sweeps = I.trace_cap;
+    a.stats = I.stats; a.err = c->err;
+    Timed tm(c, F_FLIP, s);
+    chk(flip_slice(a, c->fp64, s));
+  }
+
+  void wrap() {
+    const long bs = (long)NN();
+    GemmDesc d = gemm_desc(I.N, I.mats);
+    // T = (D G D^{-1}) e^{+dtau K}
+    d.A = I.G; d.sA = bs; d.B = I.Etp; d.sB = 0; d.C = I.Tw; d.sC = bs;
+    const size_t esz = c->fp64 ? 8 : 4;
+    d.rs = I.dv; d.srs = 2L * I.N;
+    d.ks = (char *)I.dv + esz * I.N; d.sks = 2L * I.N;
+    {
+      Timed tm(c, F_WRAP, s);
+      chk(c->fp64 ? gemm_f64(d, false, false, s) : gemm_f32(d, false, false, s));
+    }
+    // G = e^{-dtau K} T
+    GemmDesc d2 = gemm_desc(I.N, I.mats);
+    d2.A = I.Etm; d2.sA = 0; d2.B = I.Tw; d2.sB = bs; d2.C = I.G; d2.sC = bs;
+    Timed tm(c, F_WRAP, s);
+    chk(c->fp64 ? gemm_f64(d2, false, false, s) : gemm_f32(d2, false, false, s));
+  }
+
+  void stabilise(int l) {
+    const int b = (l - 1) / I.n_stab;
+    block_product(b);
+    right_update(b);
+    fresh(b, false, I.Gf);
+    Timed tm(c, F_DRIFT, s);
+    chk(drift_replace(I.G, I.Gf, I.C, I.N, c->fp64, I.stats, c->err, c->opt.drift_abort, true, s));
+  }
+
+  void slice(int l) {
+    flip(l);
+    wrap();
+    if (l % I.n_stab == 0 || l == I.Lam) stabilise(l);
+  }
+
+  void end_of_sweep() {
+    left_rebuild();
+    chk(bump_counter(I.sweep_ctr, s));
+  }
+
+  // measurement of the sweep just finished: Gf holds G(0) = G(1) fresh, the
+  // right chain after each block and the rebuilt left factors are current.
+  void measure() {
+    chk(meas_begin(I.ms, I.C, s));
+    chk(meas_docc(I.ms, I.Gf, I.C, I.N, s));
+    chk(hipMemcpyAsync(I.Gt, I.Gf, sizeof(double) * I.mats * NN(), hipMemcpyDeviceToDevice, s));
+    chk(meas_gk(I.ms, I.Gt, I.C, I.L, 0, s));
+    for (int l = 1; l <= I.Lam; ++l) {
+      if (l % I.n_stab == 0 || l == I.Lam) {
+        fresh((l - 1) / I.n_stab, true, I.Gt);      // stable G(tau_l, 0) at a block boundary
+      } else {
+        // G(tau_l, 0) = B_l G(tau_{l-1}, 0) = e^{-dtau K} diag(d_l) G(tau_{l-1}, 0)
+        chk(slice_scales(I.h, I.C, I.Lam, I.N, l, l, std::exp(I.lambda), std::exp(-I.lambda), I.dvD, s));
+        gemm64(I.Em, false, I.Gt, false, I.Pw, 0, (long)NN(), I.dvD, I.N);
+        chk(hipMemcpyAsync(I.Gt, I.Pw, sizeof(double) * I.mats * NN(), hipMemcpyDeviceToDevice, s));
+      }
+      chk(meas_gk(I.ms, I.Gt, I.C, I.L, l, s));
+    }
+    chk(meas_end(I.ms, I.C, s));
+  }
+};
+
+bss_status check_err(bss_ctx *c) {
+  if (c->poisoned) return fail(c, BSS_E_STATE, "context poisoned by an earlier numerical failure");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) { c->poisoned = true; return fail(c, BSS_E_DEVICE, std::string("device error: ") + hipGetErrorString(e)); }
+  int herr = 0;
+  e = hipMemcpy(&herr, c->err, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) { c->poisoned = true; return fail(c, BSS_E_DEVICE, hipGetErrorString(e)); }
+  if (herr & 8) { c->poisoned = true; return fail(c, BSS_E_STATE, "sweep ran past the supplied accept history"); }
+  if (herr) {
+    c->poisoned = true;
+    std::string m = "numerical failure:";
+    if (herr & 1) m += " non-positive or non-finite accepted ratio;";
+    if (herr & 2) m += " wrap drift above drift_abort;";
+    if (herr & 4) m += " non-finite recomputed Green function;";
+    return fail(c, BSS_E_NUMERICAL, m);
+  }
+  return BSS_OK;
+}
+
+bss_status usable(bss_ctx *c) {
+  if (!c) return BSS_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, BSS_E_STATE, "context poisoned by an earlier failure");
+  return BSS_OK;
+}
+
+bss_status create_impl(const bss_instance *in, int n, const bss_options *opt_in, bss_ctx **out) {
+  if (!out) return BSS_E_INVALID_ARG;
+  *out = nullptr;
+  if (!in || n < 1) return BSS_E_INVALID_ARG;
+  std::string why;
+  if (!check_options(opt_in, why)) return BSS_E_INVALID_ARG;
+  bss_options opt;
+  bss_options_default(&opt);
+  if (opt_in) opt = *opt_in;
+  std::vector<Inst> v;
+  bss_status code;
+  if (!resolve(in, n, opt, v, why, code)) return code;
+  bss_ctx *c = new (std::nothrow) bss_ctx;
+  if (!c) return BSS_E_OUT_OF_MEMORY;
+  c->opt = opt;
+  c->fp64 = opt.precision == BSS_PREC_FP64;
+  c->inst = v;
+  c->fam.resize(F_COUNT);
+  for (int f = 0; f < F_COUNT; ++f) c->fam[f].name = FAM_NAMES[f];
+  auto bail = [&](bss_status s) { bss_destroy(c); return s; };
+  if (hipGetDevice(&c->device) != hipSuccess) return bail(BSS_E_DEVICE);
+  if (opt.stream) c->stream = (hipStream_t)opt.stream;
+  else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(BSS_E_DEVICE);
+    c->own_stream = true;
+  }
+  const size_t need = total_bytes(c->inst, opt) + 4096;
+  if (opt.workspace) {
+    if (opt.workspace_bytes < need) return bail(BSS_E_OUT_OF_MEMORY);
+    c->mem = (char *)opt.workspace;
+    c->mem_bytes = opt.workspace_bytes;
+  } else {
+    if (hipMalloc(&c->mem, need) != hipSuccess) { c->mem = nullptr; return bail(BSS_E_OUT_OF_MEMORY); }
+    c->own_mem = true;
+    c->mem_bytes = need;
+  }
+  Carver cv;
+  cv.base = c->mem;
+  c->err = cv.take<int>(4);
+  c->profile = (opt.flags & BSS_FLAG_PROFILE) != 0;   // creation work is not profiled
+
+  const bool tracing = (opt.flags & (BSS_FLAG_RECORD_TRACE | BSS_FLAG_REPLAY_TRACE)) != 0;
+  for (auto &I : c->inst) layout(I, c->fp64, cv, std::max(opt.trace_sweeps, 1), tracing);
+  hipStream_t s = c->stream;
+  if (hipMemsetAsync(c->mem, 0, cv.off, s) != hipSuccess) return bail(BSS_E_DEVICE);
+  if (hipStreamSynchronize(s) != hipSuccess) return bail(BSS_E_DEVICE);
+  for (auto &I : c->inst) {
+    std::vector<int64_t> ones(I.C, 1);
+    if (hipMemcpy(I.ms.binsize, ones.data(), sizeof(int64_t) * I.C, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(BSS_E_DEVICE);
+  }
+  for (auto &I : c->inst) {
+    Exec x{c, I, s};
+    x.chk(build_exp(I.L, I.t, I.dtau, I.Em, I.Ep, c->fp64 ? nullptr : I.Etm, c->fp64 ? nullptr : I.Etp, c->fp64, s));
+    x.initialise(true);
+    if (x.e != hipSuccess) { c->last_error = hipGetErrorString(x.e); return bail(BSS_E_DEVICE); }
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) return bail(BSS_E_DEVICE);
+  for (auto &f : c->fam) {
+    for (auto &p : f.pending) { c->pool.push_back(p.first); c->pool.push_back(p.second); }
+    f.pending.clear();
+  }
+  *out = c;
+  return BSS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+void bss_options_default(bss_options *o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->struct_size = sizeof(bss_options);
+  o->precision = BSS_PREC_FP64;
+}
+
+bss_status bss_create(int32_t L, double U, double t, double beta, double dtau, uint64_t seed, int32_t n_chains,
+                      const bss_options *opt, bss_ctx **out) {
+  bss_instance in{L, U, t, beta, dtau, seed, n_chains};
+  return create_impl(&in, 1, opt, out);
+}
+
+bss_status bss_create_batch(const bss_instance *inst, int32_t n_inst, const bss_options *opt, bss_ctx **out) {
+  return create_impl(inst, n_inst, opt, out);
+}
+
+bss_status bss_workspace_size(const bss_instance *inst, int32_t n_inst, const bss_options *opt_in, size_t *bytes) {
+  if (!inst || n_inst < 1 || !bytes) return BSS_E_INVALID_ARG;
+  std::string why;
+  if (!check_options(opt_in, why)) return BSS_E_INVALID_ARG;
+  bss_options opt;
+  bss_options_default(&opt);
+  if (opt_in) opt = *opt_in;
+  std::vector<Inst> v;
+  bss_status code;
+  if (!resolve(inst, n_inst, opt, v, why, code)) return code;
+  *bytes = total_bytes(v, opt) + 4096 + 256;
+  return BSS_OK;
+}
+
+bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure) {
+  bss_status st = usable(c);
+  if (st != BSS_OK) return st;
+  if (n_sweeps < 0) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be >= 0");
+  for (auto &I : c->inst)
+    if (I.slice != 1) return fail(c, BSS_E_STATE, "an instance is part-way through a sweep");
+  for (int sw = 0; sw < n_sweeps; ++sw) {
+    for (auto &I : c->inst) {
+      Exec x{c, I, c->stream};
+      for (int l = 1; l <= I.Lam; ++l) x.slice(l);
+      x.end_of_sweep();
+      if (measure) x.measure();
+      if (x.e != hipSuccess) { c->poisoned = true; return fail(c, BSS_E_DEVICE, hipGetErrorString(x.e)); }
+      I.sweeps += 1;
+    }
+  }
+  return BSS_OK;
+}
+
+bss_status bss_step_slices(bss_ctx *c, int32_t n_slices) {
+  bss_status st = usable(c);
+  if (st != BSS_OK) return st;
+  if (n_slices < 0) return fail(c, BSS_E_INVALID_ARG, "n_slices must be >= 0");
+  for (auto &I : c->inst) {
+    Exec x{c, I, c->stream};
+    for (int n = 0; n < n_slices; ++n) {
+      x.slice(I.slice);
+      if (I.slice == I.Lam) {
+        x.end_of_sweep();
+        I.slice = 1;
+        I.sweeps += 1;
+      } else {
+        I.slice += 1;
+      }
+    }
+    if (x.e != hipSuccess) { c->poisoned = true; return fail(c, BSS_E_DEVICE, hipGetErrorString(x.e)); }
+  }
+  return BSS_OK;
+}
+
+static bss_status pick(bss_ctx *c, int32_t inst, Inst **I) {
+  bss_status st = usable(c);
+  if (st != BSS_OK) return st;
+  if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, BSS_E_INVALID_ARG, "instance index out of range");
+  *I = &c->inst[inst];
+  return BSS_OK;
+}
+
+bss_status bss_get_green(bss_ctx *c, int32_t inst, int32_t chain, int32_t spin, double *out) {
+  Inst *I;
+  bss_status st = pick(c, inst, &I);
+  if (st != BSS_OK) return st;
+  if (chain < 0 || chain >= I->C || (spin != 0 && spin != 1) || !out) return fail(c, BSS_E_INVALID_ARG, "bad chain/spin/out");
+  if ((st = check_err(c)) != BSS_OK) return st;
+  const size_t n = nn(*I);
+  const size_t off = (size_t)(2 * chain + spin) * n;
+  if (c->fp64) {
+    HIP_TRY(c, hipMemcpy(out, (double *)I->G + off, sizeof(double) * n, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> tmp(n);
+    HIP_TRY(c, hipMemcpy(tmp.data(), (float *)I->G + off, sizeof(float) * n, hipMemcpyDeviceToHost));
+    for (size_t e = 0; e < n; ++e) out[e] = tmp[e];
+  }
+  return BSS_OK;
+}
+
+bss_status bss_get_field(bss_ctx *c, int32_t inst, int32_t chain, int8_t *out) {
+  Inst *I;
+  bss_status st = pick(c, inst, &I);
+  if (st != BSS_OK) return st;
+  if (chain < 0 || chain >= I->C || !out) return fail(c, BSS_E_INVALID_ARG, "bad chain/out");
+  if ((st = check_err(c)) != BSS_OK) return st;
+  const size_t n = (size_t)I->Lam * I->N;
+  HIP_TRY(c, hipMemcpy(out, I->h + (size_t)chain * n, n, hipMemcpyDeviceToHost));
+  return BSS_OK;
+}
+
+bss_status bss_set_field(bss_ctx *c, int32_t inst, int32_t chain, const int8_t *in) {
+  Inst *I;
+  bss_status st = pick(c, inst, &I);
+  if (st != BSS_OK) return st;
+  if (chain < 0 || chain >= I->C || !in) return fail(c, BSS_E_INVALID_ARG, "bad chain/in");
+  for (auto &J : c->inst)
+    if (J.slice != 1) return fail(c, BSS_E_STATE, "set_field needs every instance at slice 1");
+  const size_t n = (size_t)I->Lam * I->N;
+  for (size_t e = 0; e < n; ++e)
+    if (in[e] != 1 && in[e] != -1) return fail(c, BSS_E_INVALID_ARG, "field entries must be +-1");
+  if ((st = check_err(c)) != BSS_OK) return st;
+  HIP_TRY(c, hipMemcpy(I->h + (size_t)chain * n, in, n, hipMemcpyHostToDevice));
+  Exec x{c, *I, c->stream};
+  x.initialise(false);
+  if (x.e != hipSuccess) { c->poisoned = true; return fail(c, BSS_E_DEVICE, hipGetErrorString(x.e)); }
+  return check_err(c);
+}
+
+bss_status bss_set_trace(bss_ctx *c, int32_t inst, const uint8_t *accept, int32_t n_sweeps) {
+  Inst *I;
+  bss_status st = pick(c, inst, &I);
+  if (st != BSS_OK) return st;
+  if (!(c->opt.flags & BSS_FLAG_REPLAY_TRACE)) return fail(c, BSS_E_STATE, "context not created with BSS_FLAG_REPLAY_TRACE");
+  if (!accept || n_sweeps < 1 || n_sweeps > I->trace_alloc) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be in 1..trace_sweeps");
+  if (I->slice != 1) return fail(c, BSS_E_STATE, "set_trace needs the instance at slice 1");
+  if ((st = check_err(c)) != BSS_OK) return st;
+  const size_t n = (size_t)n_sweeps * I->C * I->Lam * I->N;
+  HIP_TRY(c, hipMemcpy(I->trace, accept, n, hipMemcpyHostToDevice));
+  int64_t base = I->sweeps;
+  HIP_TRY(c, hipMemcpy(I->trace_base, &base, sizeof(base), hipMemcpyHostToDevice));
+  I->trace_cap = n_sweeps;   // sweeping past this window is an error
+  return BSS_OK;
+}
+
+bss_status bss_get_trace(bss_ctx *c, int32_t inst, uint8_t *accept, int32_t n_sweeps) {
+  Inst *I;
+  bss_status st = pick(c, inst, &I);
+  if (st != BSS_OK) return st;
+  if (!(c->opt.flags & BSS_FLAG_RECORD_TRACE)) return fail(c, BSS_E_STATE, "context not created with BSS_FLAG_RECORD_TRACE");
+  if (!accept || n_sweeps < 1 || n_sweeps > I->trace_cap) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be in 1..trace_sweeps");
+  if ((st = check_err(c)) != BSS_OK) return st;
+  const size_t n = (size_t)n_sweeps * I->C * I->Lam * I->N;
+  HIP_TRY(c, hipMemcpy(accept, I->trace, n, hipMemcpyDeviceToHost));
+  return BSS_OK;
+}
+
+bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
+  Inst *I;
+  bss_status st = pick(c, inst, &I);
+  if (st != BSS_OK) return st;
+  if (!out) return fail(c, BSS_E_INVALID_ARG, "out is NULL");
+  if ((st = check_err(c)) != BSS_OK) return st;
+  std::vector<ChainStats> cs(I->C);
+  HIP_TRY(c, hipMemcpy(cs.data(), I->stats, sizeof(ChainStats) * I->C, hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  out->sweeps = I->sweeps;
+  out->sign = 1;
+  double dsum = 0;
+  int64_t dcnt = 0;
+  for (auto &x : cs) {
+    out->proposals += x.proposals;
+    out->accepted += x.accepted;
+    out->logw += x.logw;
+    out->drift_max = std::max(out->drift_max, x.drift_max);
+    dsum += x.drift_sum;
+    dcnt += x.drift_count;
+  }
+  out->drift_mean = dcnt ? dsum / dcnt : 0.0;
+  out->n_chains = I->C;
+  out->N = I->N; out->Lambda = I->Lam; out->delay_k = I->k; out->n_stab = I->n_stab;
+  return BSS_OK;
+}
+
+static bss_status fetch_meas(bss_ctx *c, Inst *I, std::vector<double> &docc, std::vector<double> &gk,
+                             std::vector<int64_t> &count, std::vector<int64_t> &binsize) {
+  docc.resize((size_t)I->C * NBINS);
+  gk.resize((size_t)I->C * I->ms.nbins_g * I->ms.glen);
+  count.resize(I->C);
+  binsize.resize(I->C);
+  HIP_TRY(c, hipMemcpy(docc.data(), I->ms.docc, sizeof(double) * docc.size(), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(gk.data(), I->ms.gk, sizeof(double) * gk.size(), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(count.data(), I->ms.count, sizeof(int64_t) * I->C, hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(binsize.data(), I->ms.binsize, sizeof(int64_t) * I->C, hipMemcpyDeviceToHost));
+  return BSS_OK;
+}
+
+// mean and standard error of per-chain sums (>= 2 chains) or of the complete
+// bins of one chain; vals[c or bin][e]
+static void mean_err(const std::vector<std::vector<double>> &samples, const std::vector<double> &weights,
+                     size_t len, double *mean, double *err) {
+  const size_t S = samples.size();
+  double wsum = 0;
+  for (double w : weights) wsum += w;
+  for (size_t e = 0; e < len; ++e) {
+    double m = 0;
+    for (size_t s = 0; s < S; ++s) m += samples[s][e];
+    m /= wsum;
+    if (mean) mean[e] = m;
+    if (err) {
+      // samples[s][e] are sums over weights[s] measurements; use their means
+      double acc = 0;
+      size_t n = 0;
+      double mm = 0;
+      for (size_t s = 0; s < S; ++s) if (weights[s] > 0) { mm += samples[s][e] / weights[s]; ++n; }
+      mm = n ? mm / n : 0;
+      for (size_t s = 0; s < S; ++s) if (weights[s] > 0) { const double d = samples[s][e] / weights[s] - mm; acc += d * d; }
+      err[e] = n > 1 ? std::sqrt(acc / (n - 1) / n) : 0.0;
+    }
+  }
+}
+
+static bss_status measure_common(bss_ctx *c, int32_t inst, bool gk_wanted, double *mean, double *err, int64_t len) {
+  Inst *I;
+  bss_status st = pick(c, inst, &I);
+  if (st != BSS_OK) return st;
+  if (!mean) return fail(c, BSS_E_INVALID_ARG, "mean is NULL");
+  if (gk_wanted && len != I->ms.glen) return fail(c, BSS_E_INVALID_ARG, "len must be (Lambda+1)*N");
+  if ((st = check_err(c)) != BSS_OK) return st;
+  std::vector<double> docc, gk;
+  std::vector<int64_t> count, binsize;
+  if ((st = fetch_meas(c, I, docc, gk, count, binsize)) != BSS_OK) return st;
+  if (count[0] == 0) return fail(c, BSS_E_STATE, "no measurements accumulated");
+  const size_t glen = (size_t)I->ms.glen;
+  std::vector<std::vector<double>> samples;
+  std::vector<double> weights;
+  if (I->C >= 2) {
+    for (int ch = 0; ch < I->C; ++ch) {
+      if (gk_wanted) samples.emplace_back(gk.begin() + (size_t)ch * glen, gk.begin() + (size_t)(ch + 1) * glen);
+      else {
+        double s = 0;
+        for (int b = 0; b < NBINS; ++b) s += docc[(size_t)ch * NBINS + b];
+        samples.push_back({s});
+      }
+      weights.push_back((double)count[ch]);
+    }
+    mean_err(samples, weights, gk_wanted ? glen : 1, mean, err);
+    return BSS_OK;
+  }
+  // one chain: complete bins for the error, everything for the mean
+  const int64_t n = count[0], bs = binsize[0];
+  const int full = (int)(n / bs);
+  const int used = (int)((n + bs - 1) / bs);
+  std::vector<double> tot(gk_wanted ? glen : 1, 0.0);
+  for (int b = 0; b < used; ++b) {
+    if (gk_wanted) for (size_t e = 0; e < glen; ++e) tot[e] += gk[(size_t)b * glen + e];
+    else tot[0] += docc[b];
+  }
+  for (size_t e = 0; e < tot.size(); ++e) mean[e] = tot[e] / (double)n;
+  if (err) {
+    for (int b = 0; b < full; ++b) {
+      if (gk_wanted) samples.emplace_back(gk.begin() + (size_t)b * glen, gk.begin() + (size_t)(b + 1) * glen);
+      else samples.push_back({docc[b]});
+      weights.push_back((double)bs);
+    }
+    if (full >= 2) mean_err(samples, weights, tot.size(), nullptr, err);
+    else for (size_t e = 0; e < tot.size(); ++e) err[e] = 0.0;
+  }
+  return BSS_OK;
+}
+
+bss_status bss_measure_gtau_k(bss_ctx *c, int32_t inst, double *mean, double *err, int64_t len) {
+  return measure_common(c, inst, true, mean, err, len);
+}
+
+bss_status bss_measure_double_occ(bss_ctx *c, int32_t inst, double *mean, double *err) {
+  return measure_common(c, inst, false, mean, err, 1);
+}
+
+bss_status bss_reset_measurements(bss_ctx *c) {
+  bss_status st = usable(c);
+  if (st != BSS_OK) return st;
+  if ((st = check_err(c)) != BSS_OK) return st;
+  for (auto &I : c->inst) {
+    HIP_TRY(c, hipMemset(I.ms.docc, 0, sizeof(double) * I.C * NBINS));
+    HIP_TRY(c, hipMemset(I.ms.gk, 0, sizeof(double) * I.C * I.ms.nbins_g * I.ms.glen));
+    HIP_TRY(c, hipMemset(I.ms.count, 0, sizeof(int64_t) * I.C));
+    std::vector<int64_t> ones(I.C, 1);
+    HIP_TRY(c, hipMemcpy(I.ms.binsize, ones.data(), sizeof(int64_t) * I.C, hipMemcpyHostToDevice));
+  }
+  return BSS_OK;
+}
+
+// checkpoint layout: magic, n_inst, then per instance: C, Lam, N, sweeps,
+// field bytes, chain stats, measurement arrays and counters
+static const uint64_t CK_MAGIC = 0x31504B4353534221ull;
+
+bss_status bss_save(bss_ctx *c, void *buf, size_t *bytes) {
+  bss_status st = usable(c);
+  if (st != BSS_OK) return st;
+  if (!bytes) return fail(c, BSS_E_INVALID_ARG, "bytes is NULL");
+  size_t need = 16;
+  for (auto &I : c->inst)
+    need += 32 + (size_t)I.C * I.Lam * I.N + sizeof(ChainStats) * I.C + sizeof(double) * I.C * NBINS +
+            sizeof(double) * I.C * I.ms.nbins_g * I.ms.glen + 2 * sizeof(int64_t) * I.C;
+  if (!buf) { *bytes = need; return BSS_OK; }
+  if (*bytes < need) return fail(c, BSS_E_INVALID_ARG, "buffer too small");
+  for (auto &I : c->inst)
+    if (I.slice != 1) return fail(c, BSS_E_STATE, "save needs every instance at slice 1");
+  if ((st = check_err(c)) != BSS_OK) return st;
+  char *p = (char *)buf;
+  auto put = [&](const void *src, size_t n) { std::memcpy(p, src, n); p += n; };
+  uint64_t hdr[2] = {CK_MAGIC, (uint64_t)c->inst.size()};
+  put(hdr, 16);
+  for (auto &I : c->inst) {
+    int64_t meta[4] = {I.C, I.Lam, I.N, I.sweeps};
+    put(meta, 32);
+    HIP_TRY(c, hipMemcpy(p, I.h, (size_t)I.C * I.Lam * I.N, hipMemcpyDeviceToHost)); p += (size_t)I.C * I.Lam * I.N;
+    HIP_TRY(c, hipMemcpy(p, I.stats, sizeof(ChainStats) * I.C, hipMemcpyDeviceToHost)); p += sizeof(ChainStats) * I.C;
+    HIP_TRY(c, hipMemcpy(p, I.ms.docc, sizeof(double) * I.C * NBINS, hipMemcpyDeviceToHost)); p += sizeof(double) * I.C * NBINS;
+    const size_t g = sizeof(double) * I.C * I.ms.nbins_g * I.ms.glen;
+    HIP_TRY(c, hipMemcpy(p, I.ms.gk, g, hipMemcpyDeviceToHost)); p += g;
+    HIP_TRY(c, hipMemcpy(p, I.ms.count, sizeof(int64_t) * I.C, hipMemcpyDeviceToHost)); p += sizeof(int64_t) * I.C;
+    HIP_TRY(c, hipMemcpy(p, I.ms.binsize, sizeof(int64_t) * I.C, hipMemcpyDeviceToHost)); p += sizeof(int64_t) * I.C;
+  }
+  *bytes = (size_t)(p - (char *)buf);
+  return BSS_OK;
+}
+
+bss_status bss_load(bss_ctx *c, const void *buf, size_t bytes) {
+  bss_status st = usable(c);
+  if (st != BSS_OK) return st;
+  if (!buf || bytes < 16) return fail(c, BSS_E_INVALID_ARG, "bad checkpoint buffer");
+  const char *p = (const char *)buf, *end = p + bytes;
+  uint64_t hdr[2];
+  std::memcpy(hdr, p, 16); p += 16;
+  if (hdr[0] != CK_MAGIC || hdr[1] != c->inst.size()) return fail(c, BSS_E_INVALID_ARG, "checkpoint does not match this context");
+  if ((st = check_err(c)) != BSS_OK) return st;
+  for (auto &I : c->inst) {
+    if (end - p < 32) return fail(c, BSS_E_INVALID_ARG, "truncated checkpoint");
+    int64_t meta[4];
+    std::memcpy(meta, p, 32); p += 32;
+    if (meta[0] != I.C || meta[1] != I.Lam || meta[2] != I.N) return fail(c, BSS_E_INVALID_ARG, "checkpoint instance mismatch");
+    const size_t g = sizeof(double) * I.C * I.ms.nbins_g * I.ms.glen;
+    const size_t need = (size_t)I.C * I.Lam * I.N + sizeof(ChainStats) * I.C + sizeof(double) * I.C * NBINS + g +
+                        2 * sizeof(int64_t) * I.C;
+    if ((size_t)(end - p) < need) return fail(c, BSS_E_INVALID_ARG, "truncated checkpoint");
+    const int8_t *hf = (const int8_t *)p;
+    for (size_t e = 0; e < (size_t)I.C * I.Lam * I.N; ++e)
+      if (hf[e] != 1 && hf[e] != -1) return fail(c, BSS_E_INVALID_ARG, "corrupt field in checkpoint");
+    HIP_TRY(c, hipMemcpy(I.h, p, (size_t)I.C * I.Lam * I.N, hipMemcpyHostToDevice)); p += (size_t)I.C * I.Lam * I.N;
+    HIP_TRY(c, hipMemcpy(I.stats, p, sizeof(ChainStats) * I.C, hipMemcpyHostToDevice)); p += sizeof(ChainStats) * I.C;
+    HIP_TRY(c, hipMemcpy(I.ms.docc, p, sizeof(double) * I.C * NBINS, hipMemcpyHostToDevice)); p += sizeof(double) * I.C * NBINS;
+    HIP_TRY(c, hipMemcpy(I.ms.gk, p, g, hipMemcpyHostToDevice)); p += g;
+    HIP_TRY(c, hipMemcpy(I.ms.count, p, sizeof(int64_t) * I.C, hipMemcpyHostToDevice)); p += sizeof(int64_t) * I.C;
+    HIP_TRY(c, hipMemcpy(I.ms.binsize, p, sizeof(int64_t) * I.C, hipMemcpyHostToDevice)); p += sizeof(int64_t) * I.C;
+    I.sweeps = meta[3];
+    I.slice = 1;
+    HIP_TRY(c, hipMemcpy(I.sweep_ctr, &I.sweeps, sizeof(int64_t), hipMemcpyHostToDevice));
+    Exec x{c, I, c->stream};
+    x.initialise(false);
+    if (x.e != hipSuccess) { c->poisoned = true; return fail(c, BSS_E_DEVICE, hipGetErrorString(x.e)); }
+  }
+  return check_err(c);
+}
+
+bss_status bss_get_profile(bss_ctx *c, bss_kernel_time *out, int32_t cap, int32_t *n_out) {
+  bss_status st = usable(c);
+  if (st != BSS_OK) return st;
+  if (!c->profile) return fail(c, BSS_E_STATE, "context not created with BSS_FLAG_PROFILE");
+  if (cap < 0 || (cap > 0 && !out)) return fail(c, BSS_E_INVALID_ARG, "bad output buffer");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (auto &f : c->fam) {
+    for (auto &p : f.pending) {
+      float ms = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&ms, p.first, p.second));
+      f.ms += ms;
+      f.launches += 1;
+      c->pool.push_back(p.first);
+      c->pool.push_back(p.second);
+    }
+    f.pending.clear();
+  }
+  int n = 0;
+  for (auto &f : c->fam) {
+    if (n < cap) {
+      std::memset(&out[n], 0, sizeof(bss_kernel_time));
+      std::snprintf(out[n].name, sizeof(out[n].name), "%s", f.name);
+      out[n].launches = f.launches;
+      out[n].total_ms = f.ms;
+    }
+    ++n;
+  }
+  if (n_out) *n_out = n;
+  return BSS_OK;
+}
+
+bss_status bss_reset_profile(bss_ctx *c) {
+  bss_status st = usable(c);
+  if (st != BSS_OK) return st;
+  if (!c->profile) return fail(c, BSS_E_STATE, "context not created with BSS_FLAG_PROFILE");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (auto &f : c->fam) {
+    for (auto &p : f.pending) { c->pool.push_back(p.first); c->pool.push_back(p.second); }
+    f.pending.clear();
+    f.launches = 0;
+    f.ms = 0.0;
+  }
+  return BSS_OK;
+}
+
+void bss_destroy(bss_ctx *c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  for (auto &f : c->fam)
+    for (auto &p : f.pending) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
+  for (auto e : c->pool) hipEventDestroy(e);
+  if (c->own_mem && c->mem) hipFree(c->mem);
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char *bss_status_string(bss_status s) {
+  switch (s) {
+    case BSS_OK: return "ok";
+    case BSS_E_INVALID_ARG: return "invalid argument";
+    case BSS_E_UNSUPPORTED: return "unsupported";
+    case BSS_E_OUT_OF_MEMORY: return "out of memory";
+    case BSS_E_DEVICE: return "device error";
+    case BSS_E_NUMERICAL: return "numerical failure";
+    case BSS_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char *bss_last_error(const bss_ctx *c) { return c ? c->last_error.c_str() : ""; }
+
+}  // extern "C"

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+declared in include/bssqmc.h, and rejects invalid arguments before touching a
+device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1504_05090_amd as bss
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "bssqmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bss_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(bss.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = bss.lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = bss.lib()
+    for s in range(7):
+        assert L.bss_status_string(s)
+    assert L.bss_last_error(None) == b""
+
+
+def _create(L_, U=2.0, t=0.25, beta=4.0, dtau=0.5, chains=1, opt=None):
+    h = ctypes.c_void_p()
+    st = bss.lib().bss_create(L_, U, t, beta, dtau, 1, chains, opt, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("args,status", [
+    (dict(L_=1), bss.BSS_E_INVALID_ARG),
+    (dict(L_=4, U=-1.0), bss.BSS_E_INVALID_ARG),
+    (dict(L_=4, beta=0.0), bss.BSS_E_INVALID_ARG),
+    (dict(L_=4, dtau=-0.5), bss.BSS_E_INVALID_ARG),
+    (dict(L_=4, beta=4.1), bss.BSS_E_INVALID_ARG),
+    (dict(L_=4, chains=0), bss.BSS_E_INVALID_ARG),
+    (dict(L_=4, U=float("nan")), bss.BSS_E_INVALID_ARG),
+    (dict(L_=5), bss.BSS_E_UNSUPPORTED),
+    (dict(L_=24), bss.BSS_E_UNSUPPORTED),
+])
+def test_create_rejects_invalid_arguments(args, status):
+    st, h = _create(**args)
+    assert st == status
+    assert not h.value
+
+
+def test_bad_options_rejected():
+    o = bss.make_options()
+    o.struct_size = 3
+    st, _ = _create(4, opt=ctypes.byref(o))
+    assert st == bss.BSS_E_INVALID_ARG
+    o = bss.make_options(flags=bss.FLAG_RECORD_TRACE | bss.FLAG_REPLAY_TRACE, trace_sweeps=1)
+    assert _create(4, opt=ctypes.byref(o))[0] == bss.BSS_E_INVALID_ARG
+    o = bss.make_options(delay_k=65)
+    assert _create(4, opt=ctypes.byref(o))[0] == bss.BSS_E_INVALID_ARG
+
+
+def test_workspace_size_is_host_only():
+    inst = (bss.Instance * 2)(bss.Instance(4, 2.0, 0.25, 4.0, 0.5, 1, 1), bss.Instance(8, 2.0, 0.25, 10.0, 0.5, 1, 64))
+    n = ctypes.c_size_t()
+    o = bss.make_options()
+    assert bss.lib().bss_workspace_size(inst, 2, ctypes.byref(o), ctypes.byref(n)) == bss.BSS_OK
+    one = ctypes.c_size_t()
+    assert bss.lib().bss_workspace_size(inst, 1, ctypes.byref(o), ctypes.byref(one)) == bss.BSS_OK
+    assert n.value > one.value > 0
+
+
+def test_null_safe_calls():
+    L = bss.lib()
+    L.bss_destroy(None)
+    assert L.bss_sweep(None, 1, 0) == bss.BSS_E_INVALID_ARG
+
+
+def test_create_without_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, h = _create(4)
+    assert st == bss.BSS_E_DEVICE and not h.value
+    with pytest.raises(bss.BssError):
+        bss.Context([dict(L=4, U=2.0, beta=4.0, dtau=0.5, seed=1, n_chains=1)])
