@@ -25,48 +25,63 @@ namespace bss {
 
 namespace {
 
-constexpr int FB = 64;  // rows of X staged per flush block
-
-// G0 <- G0 - X Y^T for one spin.  X rows [i0, i0+FB) are staged into LDS by
-// their owners; Y^T columns come from the owners of the output columns.  The
-// block product runs on 16x16x4 MFMA tiles: wavefront w handles output
-// columns [16 w', 16 w' + 16) for w' = w, w + nw, ... of each row block.
+// G0 <- G0 - X Y^T for one spin, on 16x16x4 MFMA tiles with the G0 tile as
+// the accumulator input (D = (-X) Y^T + G0).  Rows of -X are staged in LDS
+// by their owners in blocks of fb rows, Y^T once; each wavefront loads a
+// batch of G0 tiles before its MFMAs so that the global latencies overlap.
 template <typename T, int KM>
-__device__ void flush_spin(T *G, int N, const T (&xs)[KM], const T (&ys)[KM], T *Xs, T *Ys) {
+__device__ void flush_spin(T *G, int N, int fb, const T (&xs)[KM], const T (&ys)[KM], T *Xs, T *Ys) {
+  constexpr int TB = 8;   // tiles in flight per wavefront
   const int j = threadIdx.x, lane = j & 63, w = j >> 6, nw = blockDim.x >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int ldy = blockDim.x + 1;
   const bool own = j < N;
-  // Y^T staged once: Ys[s][col]
 #pragma unroll
-  for (int s = 0; s < KM; ++s) Ys[s * (blockDim.x + 1) + j] = own ? ys[s] : (T)0;
+  for (int s = 0; s < KM; ++s) Ys[s * ldy + j] = own ? ys[s] : (T)0;
   typedef typename Mfma<T>::acc_t acc_t;
-  for (int i0 = 0; i0 < N; i0 += FB) {
+  const int ctiles = (N + 15) >> 4;
+  for (int i0 = 0; i0 < N; i0 += fb) {
     __syncthreads();
-    if (j >= i0 && j < i0 + FB) {
+    if (j >= i0 && j < i0 + fb) {
 #pragma unroll
-      for (int s = 0; s < KM; ++s) Xs[(j - i0) * (KM + 1) + s] = own ? xs[s] : (T)0;
+      for (int s = 0; s < KM; ++s) Xs[(j - i0) * (KM + 1) + s] = own ? -xs[s] : (T)0;
     }
     __syncthreads();
-    const int nrb = min(FB, N - i0);
-    // tiles: (row block of 16) x (column block of 16)
-    const int rtiles = (nrb + 15) >> 4, ctiles = (N + 15) >> 4;
-    for (int tile = w; tile < rtiles * ctiles; tile += nw) {
-      const int tr = tile / ctiles, tc = tile % ctiles;
-      acc_t acc = acc_t{0, 0, 0, 0};
+    const int nrb = min(fb, N - i0);
+    const int ntiles = ((nrb + 15) >> 4) * ctiles;
+    for (int base = w; base < ntiles; base += nw * TB) {
+      acc_t acc[TB];
 #pragma unroll
-      for (int s0 = 0; s0 < KM; s0 += 4) {
-        const int s = s0 + (lane >> 4);
-        T a = (T)0, b = (T)0;
-        if (s < KM) {
-          a = Xs[(tr * 16 + (lane & 15)) * (KM + 1) + s];
-          b = Ys[s * (blockDim.x + 1) + tc * 16 + (lane & 15)];
+      for (int b = 0; b < TB; ++b) {
+        const int tile = base + nw * b;
+        const int tr = tile / ctiles, tc = tile % ctiles;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = i0 + tr * 16 + Mfma<T>::row(lane, r), col = tc * 16 + l16;
+          acc[b][r] = (tile < ntiles && row < i0 + nrb && col < N) ? G[(long)row * N + col] : (T)0;
         }
-        acc = Mfma<T>::mac(a, b, acc);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = i0 + tr * 16 + Mfma<T>::row(lane, r);
-        const int col = tc * 16 + (lane & 15);
-        if (row < i0 + nrb && col < N) G[(long)row * N + col] -= acc[r];
+      for (int b = 0; b < TB; ++b) {
+        const int tile = base + nw * b;
+        if (tile < ntiles) {
+          const int tr = tile / ctiles, tc = tile % ctiles;
+#pragma unroll
+          for (int s0 = 0; s0 < KM; s0 += 4) {
+            const int s = s0 + lq;
+            T a = (T)0, bb = (T)0;
+            if (s < KM) {
+              a = Xs[(tr * 16 + l16) * (KM + 1) + s];
+              bb = Ys[s * ldy + tc * 16 + l16];
+            }
+            acc[b] = Mfma<T>::mac(a, bb, acc[b]);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = i0 + tr * 16 + Mfma<T>::row(lane, r), col = tc * 16 + l16;
+            if (row < i0 + nrb && col < N) G[(long)row * N + col] = acc[b][r];
+          }
+        }
       }
     }
   }
@@ -76,8 +91,8 @@ __device__ void flush_spin(T *G, int N, const T (&xs)[KM], const T (&ys)[KM], T 
 template <typename T, int KM, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
   extern __shared__ char smem_raw[];
-  T *Xs = (T *)smem_raw;                                  // [FB][KM+1]
-  T *Ys = Xs + FB * (KM + 1);                             // [KM][blockDim+1]
+  T *Xs = (T *)smem_raw;                                  // [fb][KM+1]
+  T *Ys = Xs + a.fb * (KM + 1);                           // [KM][blockDim+1]
   __shared__ int first[16];
   __shared__ T bX[2][KM], bY[2][KM];
   __shared__ double bF[2];
@@ -151,14 +166,18 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
       mine = true;
     }
     __syncthreads();
+    // row ist and column ist of G0 for both spins: four independent loads
+    T gr[2] = {(T)0, (T)0}, gc[2] = {(T)0, (T)0};
+    if (own) {
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) {
+        gr[sp] = G[sp][(long)ist * N + j];
+        gc[sp] = G[sp][(long)j * N + ist];
+      }
+    }
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp) {
-      T gr = 0, gc = 0;
-      if (own) {
-        gr = G[sp][(long)ist * N + j];
-        gc = G[sp][(long)j * N + ist];
-      }
-      T cv = gc, rv = gr;
+      T cv = gc[sp], rv = gr[sp];
 #pragma unroll
       for (int s = 0; s < KM; ++s) {
         cv -= xs[sp][s] * bY[sp][s];
@@ -175,8 +194,8 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
     ++m;
     pos = ist + 1;
     if (m == a.k) {
-      flush_spin<T, KM>(G[0], N, xs[0], ys[0], Xs, Ys);
-      flush_spin<T, KM>(G[1], N, xs[1], ys[1], Xs, Ys);
+      flush_spin<T, KM>(G[0], N, a.fb, xs[0], ys[0], Xs, Ys);
+      flush_spin<T, KM>(G[1], N, a.fb, xs[1], ys[1], Xs, Ys);
 #pragma unroll
       for (int s = 0; s < KM; ++s) { xs[0][s] = xs[1][s] = ys[0][s] = ys[1][s] = (T)0; }
       d[0] = own ? (double)G[0][(long)j * N + j] : 0.0;
@@ -186,8 +205,8 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
     __syncthreads();
   }
   if (m > 0) {
-    flush_spin<T, KM>(G[0], N, xs[0], ys[0], Xs, Ys);
-    flush_spin<T, KM>(G[1], N, xs[1], ys[1], Xs, Ys);
+    flush_spin<T, KM>(G[0], N, a.fb, xs[0], ys[0], Xs, Ys);
+    flush_spin<T, KM>(G[1], N, a.fb, xs[1], ys[1], Xs, Ys);
   }
   // diagonal factors of the updated slice for the wrap: D = e^{sigma lambda h}
   if (own) {
@@ -210,9 +229,16 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
 }
 
 template <typename T, int KM>
-hipError_t launch_k(const FlipArgs &a, hipStream_t s) {
+hipError_t launch_k(const FlipArgs &a0, hipStream_t s) {
+  FlipArgs a = a0;
   const int threads = ((a.N + 63) / 64) * 64;
-  const size_t lds = sizeof(T) * ((size_t)FB * (KM + 1) + (size_t)KM * (threads + 1));
+  // rows of X staged per flush block: as many as fit next to Y^T in ~150 KB
+  const size_t ybytes = sizeof(T) * (size_t)KM * (threads + 1);
+  const size_t budget = 150 * 1024;
+  int fb = 16;
+  while (fb < a.N && ybytes + sizeof(T) * (size_t)(fb + 16) * (KM + 1) <= budget) fb += 16;
+  a.fb = fb;
+  const size_t lds = sizeof(T) * (size_t)fb * (KM + 1) + ybytes;
   if (threads <= 256)
     hipLaunchKernelGGL((k_flip<T, KM, 256>), dim3(a.chains), dim3(threads), lds, s, a);
   else if (threads <= 512)

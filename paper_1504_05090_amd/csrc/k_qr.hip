@@ -1,0 +1,509 @@
+// Blocked Householder QR in FP64 for the UDV stabilisation (gfx950).
+//
+// One workgroup factors one matrix of the batch.  Columns are processed in
+// panels of NB.  A panel is factored in LDS (unblocked Householder with
+// wavefront reductions for the norms), its reflectors are aggregated into the
+// compact WY form Q_p = I - V T V^T (Schreiber & Van Loan), and the trailing
+// columns are updated chunk by chunk with two FP64 MFMA products,
+//   W = V^T C,   C <- C - V (T^T W),
+// the chunk C staying in registers in the MFMA accumulator layout.
+//
+// Pivoting for the UDV factorisation: before each panel the remaining columns
+// are ranked by their current norms (accumulated while the previous panel's
+// update streams through them) and the NB largest are swapped into the panel.
+// For the graded products X = P U D this orders the scales as Businger-Golub
+// column pivoting does, at the cost of one norm per column per panel.
+//
+//   qr_udv:   X Pi = Q R  ->  U = Q, D = diag R, RP = D^{-1} R Pi^T
+//   qr_solve: M Z = B by M = Q R (no pivoting), Z = R^{-1} Q^T B
+#include "common.h"
+#include "kernels.h"
+
+namespace bss {
+
+namespace {
+
+constexpr int QT = 256;   // 4 wavefronts
+typedef Mfma<double> M64;
+
+// per-shape constants: panel width NB, chunk width CW, max row tiles per wave
+template <int NB_, int CW_, int RTW_> struct Shape {
+  static constexpr int NB = NB_, CW = CW_, RTW = RTW_;
+  static constexpr int LDV = NB + 1;
+  static constexpr int CT = CW / 16;   // column tiles per chunk
+  static constexpr int WT = NB / 16;   // row tiles of W
+};
+typedef Shape<32, 64, 4> ShapeS;   // N <= 256
+typedef Shape<16, 32, 8> ShapeL;   // N <= 512
+
+struct Lds {
+  double *V;      // [mr][LDV] panel / clean reflectors
+  double *Wp;     // [4][NB][CW] per-wave partials of V^T C
+  double *W2;     // [NB][CW]   -op(T) W
+  double *T;      // [NB][NB]
+  double *tau;    // [NB]
+  double *beta;   // [NB]
+  double *red;    // [64]
+  double *norms;  // [N]  current column norms (udv)
+  double *npart;  // [4][CW] per-wave partial norms (aliases the spare partials of Wp)
+  int *orig;      // [N]  original index of each physical column (udv)
+  int *sel;       // [N]  scratch for the panel selection
+};
+
+__device__ __forceinline__ int round16(int x) { return (x + 15) & ~15; }
+
+template <class S>
+__device__ Lds carve(char *base, int N) {
+  Lds s;
+  const int mr = round16(N);
+  double *p = (double *)base;
+  s.V = p; p += mr * S::LDV;
+  s.Wp = p; p += 4 * S::NB * S::CW;
+  s.W2 = p; p += S::NB * S::CW;
+  s.T = p; p += S::NB * S::NB;
+  s.tau = p; p += S::NB;
+  s.beta = p; p += S::NB;
+  s.red = p; p += 64;
+  s.norms = p; p += N;
+  s.npart = s.Wp + S::NB * S::CW;   // partial 1..3 of Wp are free once W is summed
+  s.orig = (int *)p;
+  s.sel = s.orig + N;
+  return s;
+}
+
+template <class S>
+size_t lds_bytes(int N) {
+  const int mr = (N + 15) & ~15;
+  const size_t d = (size_t)mr * S::LDV + 4 * S::NB * S::CW + S::NB * S::CW + S::NB * S::NB + 2 * S::NB + 64 + N;
+  return d * sizeof(double) + 2 * sizeof(int) * N;
+}
+
+// Unblocked Householder on the LDS panel V[0..m) x [0..w): on return the
+// strict lower part holds v (v_j = 1 implicit), beta[j] = R_jj, tau[j].
+template <class S>
+__device__ void panel_factor(const Lds &s, int m, int w) {
+  constexpr int LDV = S::LDV;
+  const int t = threadIdx.x;
+  for (int j = 0; j < w; ++j) {
+    double part = 0.0;
+    for (int r = j + 1 + t; r < m; r += QT) { const double x = s.V[r * LDV + j]; part += x * x; }
+    const double xn2 = block_sum(part, s.red);
+    const double x0 = s.V[j * LDV + j];
+    double tj = 0.0, bj = x0, scale = 0.0;
+    if (xn2 > 0.0) {
+      bj = (x0 >= 0.0 ? -1.0 : 1.0) * sqrt(x0 * x0 + xn2);
+      tj = (bj - x0) / bj;
+      scale = 1.0 / (x0 - bj);
+    }
+    __syncthreads();
+    for (int r = j + 1 + t; r < m; r += QT) s.V[r * LDV + j] *= scale;
+    if (t == 0) { s.tau[j] = tj; s.beta[j] = bj; }
+    __syncthreads();
+    if (tj != 0.0) {   // columns q > j of the panel, 8 threads per column
+      const int q = j + 1 + (t >> 3), sub = t & 7;
+      double acc = 0.0;
+      if (q < w) {
+        acc = (sub == 0) ? s.V[j * LDV + q] : 0.0;
+        for (int r = j + 1 + sub; r < m; r += 8) acc += s.V[r * LDV + j] * s.V[r * LDV + q];
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      acc += __shfl_xor(acc, 4, 64);
+      if (q < w) {
+        const double f = tj * acc;
+        if (sub == 0) s.V[j * LDV + q] -= f;
+        for (int r = j + 1 + sub; r < m; r += 8) s.V[r * LDV + q] -= f * s.V[r * LDV + j];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Write the factored panel to global (R on and above the diagonal, v below)
+// and turn LDS V into the clean reflector block (1 on the diagonal, zeros
+// above and in the padding up to mr x NB).
+template <class S>
+__device__ void panel_store_clean(const Lds &s, double *A, int N, int c0, int m, int w, int mr) {
+  constexpr int LDV = S::LDV;
+  for (int e = threadIdx.x; e < m * w; e += QT) {
+    const int r = e / w, q = e % w;
+    A[(long)(c0 + r) * N + c0 + q] = (r == q) ? s.beta[q] : s.V[r * LDV + q];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < mr * S::NB; e += QT) {
+    const int r = e / S::NB, q = e % S::NB;
+    const double v = (q >= w || r >= m || r < q) ? 0.0 : (r == q ? 1.0 : s.V[r * LDV + q]);
+    s.V[r * LDV + q] = v;
+  }
+  __syncthreads();
+}
+
+template <class S>
+__device__ void panel_load_clean(const Lds &s, const double *A, int N, int c0, int m, int w, int mr) {
+  constexpr int LDV = S::LDV;
+  for (int e = threadIdx.x; e < mr * S::NB; e += QT) {
+    const int r = e / S::NB, q = e % S::NB;
+    const double v = (q >= w || r >= m || r < q) ? 0.0 : (r == q ? 1.0 : A[(long)(c0 + r) * N + c0 + q]);
+    s.V[r * LDV + q] = v;
+  }
+  __syncthreads();
+}
+
+// T (upper triangular) of Q_p = I - V T V^T:
+// T_jj = tau_j,  T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j).
+template <class S>
+__device__ void build_T(const Lds &s, int m, int w) {
+  constexpr int LDV = S::LDV, NB = S::NB;
+  const int t = threadIdx.x;
+  double *gram = s.Wp;
+  for (int e = t; e < NB * NB; e += QT) {
+    const int i = e / NB, j = e % NB;
+    double acc = 0.0;
+    if (i < j && j < w)
+      for (int r = j; r < m; ++r) acc += s.V[r * LDV + i] * s.V[r * LDV + j];
+    gram[e] = acc;
+    s.T[e] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    double v = 0.0;
+    if (t < j)
+      for (int q = t; q < j; ++q) v += s.T[t * NB + q] * gram[q * NB + j];
+    __syncthreads();
+    if (t < j) s.T[t * NB + j] = -s.tau[j] * v;
+    if (t == 0) s.T[j * NB + j] = s.tau[j];
+    __syncthreads();
+  }
+}
+
+// Apply (I - V op(T) V^T) to columns [c0, c1) of X (rows r0..r0+m), row
+// stride ldx.  TRANS_T: op(T) = T^T (Q_p^T, used while factoring), else T
+// (Q_p, used to form Q).  With NORMS, the squared norms of the updated
+// columns over rows >= r0 + nskip are left in s.norms[col].
+template <class S, bool TRANS_T, bool NORMS>
+__device__ void apply_block(const Lds &s, double *X, long ldx, int r0, int m, int mr, int c0, int c1, int nskip) {
+  constexpr int LDV = S::LDV, NB = S::NB, CW = S::CW, CT = S::CT, WT = S::WT, RTW = S::RTW;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int rtiles = mr / 16;
+  for (int cc = c0; cc < c1; cc += CW) {
+    // 1. chunk into registers (accumulator layout): tile (rt, u), reg r holds
+    //    row 16 rt + lq + 4 r, column cc + 16 u + l16
+    M64::acc_t cr[RTW][CT];
+#pragma unroll
+    for (int a = 0; a < RTW; ++a) {
+      const int rt = wv + 4 * a;
+#pragma unroll
+      for (int u = 0; u < CT; ++u) {
+        const int col = cc + 16 * u + l16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * rt + lq + 4 * r;
+          cr[a][u][r] = (rt < rtiles && row < m && col < c1) ? X[(long)(r0 + row) * ldx + col] : 0.0;
+        }
+      }
+    }
+    // 2. this wave's partial W = V^T C over its row tiles
+    M64::acc_t wacc[WT][CT];
+#pragma unroll
+    for (int i = 0; i < WT; ++i)
+#pragma unroll
+      for (int u = 0; u < CT; ++u) wacc[i][u] = M64::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < RTW; ++a) {
+      const int rt = wv + 4 * a;
+      if (rt < rtiles) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int k = 16 * rt + 4 * st + lq;
+#pragma unroll
+          for (int i = 0; i < WT; ++i) {
+            const double av = s.V[k * LDV + 16 * i + l16];
+#pragma unroll
+            for (int u = 0; u < CT; ++u) wacc[i][u] = M64::mac(av, cr[a][u][st], wacc[i][u]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < WT; ++i)
+#pragma unroll
+      for (int u = 0; u < CT; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s.Wp[(wv * NB + 16 * i + M64::row(lane, r)) * CW + 16 * u + l16] = wacc[i][u][r];
+    __syncthreads();
+    // 3. W = sum of partials; W2 = -op(T) W
+    for (int e = t; e < NB * CW; e += QT)
+      s.Wp[e] = (s.Wp[e] + s.Wp[NB * CW + e]) + (s.Wp[2 * NB * CW + e] + s.Wp[3 * NB * CW + e]);
+    __syncthreads();
+    for (int e = t; e < NB * CW; e += QT) {
+      const int i = e / CW, q = e % CW;
+      double acc = 0.0;
+      if (TRANS_T) {
+        for (int k = 0; k <= i; ++k) acc += s.T[k * NB + i] * s.Wp[k * CW + q];
+      } else {
+        for (int k = i; k < NB; ++k) acc += s.T[i * NB + k] * s.Wp[k * CW + q];
+      }
+      s.W2[e] = -acc;
+    }
+    __syncthreads();
+    // 4. C += V W2 in registers, store, optional norms
+    double nrm[CT];
+#pragma unroll
+    for (int u = 0; u < CT; ++u) nrm[u] = 0.0;
+#pragma unroll
+    for (int a = 0; a < RTW; ++a) {
+      const int rt = wv + 4 * a;
+      if (rt < rtiles) {
+#pragma unroll
+        for (int k0 = 0; k0 < NB; k0 += 4) {
+          const double av = s.V[(16 * rt + l16) * LDV + k0 + lq];
+#pragma unroll
+          for (int u = 0; u < CT; ++u) cr[a][u] = M64::mac(av, s.W2[(k0 + lq) * CW + 16 * u + l16], cr[a][u]);
+        }
+#pragma unroll
+        for (int u = 0; u < CT; ++u) {
+          const int col = cc + 16 * u + l16;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * rt + lq + 4 * r;
+            if (row < m && col < c1) {
+              X[(long)(r0 + row) * ldx + col] = cr[a][u][r];
+              if (NORMS && row >= nskip) nrm[u] += cr[a][u][r] * cr[a][u][r];
+            }
+          }
+        }
+      }
+    }
+    if (NORMS) {
+#pragma unroll
+      for (int u = 0; u < CT; ++u) {
+        double v = nrm[u];
+        v += __shfl_xor(v, 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        if (lq == 0) s.npart[wv * CW + 16 * u + l16] = v;
+      }
+      __syncthreads();
+      for (int q = t; q < CW; q += QT)
+        if (cc + q < c1) s.norms[cc + q] = (s.npart[q] + s.npart[CW + q]) + (s.npart[2 * CW + q] + s.npart[3 * CW + q]);
+    }
+    __syncthreads();
+  }
+}
+
+// Swap the NB remaining columns of largest current norm (ties: lower physical
+// index first) into positions [c0, c0 + w), in order of decreasing norm.
+template <class S>
+__device__ void select_panel(const Lds &s, double *A, double *scratch, int N, int c0, int w) {
+  const int t = threadIdx.x;
+  // rank among the remaining columns
+  for (int q = c0 + t; q < N; q += QT) {
+    const double nq = s.norms[q];
+    int rank = 0;
+    for (int p = c0; p < N; ++p) rank += (s.norms[p] > nq) || (s.norms[p] == nq && p < q);
+    s.sel[q] = rank;
+  }
+  __syncthreads();
+  // chosen column with rank r goes to position c0 + r; the displaced columns
+  // (not chosen, sitting in [c0, c0+w)) fill the vacated positions in order
+  if (t == 0) {
+    int nd = 0;
+    // reuse orig-like bookkeeping in the sel array beyond N is not available:
+    // build the move list sequentially (w <= 32 entries)
+    int src[32], dst[32];
+    int vac[32], nv = 0, dis[32];
+    for (int q = c0; q < N; ++q) {
+      const int r = s.sel[q];
+      if (r < w) { src[r] = q; if (q >= c0 + w) vac[nv++] = q; }
+    }
+    for (int q = c0; q < c0 + w; ++q)
+      if (s.sel[q] >= w) dis[nd++] = q;
+    // encode moves into sel[0..2w): sel[i] = from, sel[w + i] = to
+    for (int r = 0; r < w; ++r) { s.sel[r] = src[r]; s.sel[w + r] = c0 + r; }
+    for (int i = 0; i < nd; ++i) { s.sel[2 * w + i] = dis[i]; s.sel[3 * w + i] = vac[i]; }
+    s.sel[4 * w] = nd;
+  }
+  __syncthreads();
+  const int nd = s.sel[4 * w];
+  // copy the chosen columns out (all rows), then move displaced ones, then write back
+  for (int e = t; e < N * w; e += QT) {
+    const int r = e / w, i = e % w;
+    scratch[(long)r * 32 + i] = A[(long)r * N + s.sel[i]];
+  }
+  __syncthreads();
+  for (int e = t; e < N * nd; e += QT) {
+    const int r = e / nd, i = e % nd;
+    A[(long)r * N + s.sel[3 * w + i]] = A[(long)r * N + s.sel[2 * w + i]];
+  }
+  __syncthreads();
+  for (int e = t; e < N * w; e += QT) {
+    const int r = e / w, i = e % w;
+    A[(long)r * N + c0 + i] = scratch[(long)r * 32 + i];
+  }
+  // bookkeeping of original indices and norms (single thread, w <= 32 moves)
+  if (t == 0) {
+    int o_src[32], o_dis[32];
+    double n_src[32], n_dis[32];
+    for (int i = 0; i < w; ++i) { o_src[i] = s.orig[s.sel[i]]; n_src[i] = s.norms[s.sel[i]]; }
+    for (int i = 0; i < nd; ++i) { o_dis[i] = s.orig[s.sel[2 * w + i]]; n_dis[i] = s.norms[s.sel[2 * w + i]]; }
+    for (int i = 0; i < nd; ++i) { s.orig[s.sel[3 * w + i]] = o_dis[i]; s.norms[s.sel[3 * w + i]] = n_dis[i]; }
+    for (int i = 0; i < w; ++i) { s.orig[c0 + i] = o_src[i]; s.norms[c0 + i] = n_src[i]; }
+  }
+  __syncthreads();
+}
+
+// factor A (N x N, in place) panel by panel; T of panel p saved to Tsave.
+// PIVOT: panel selection by current norms (udv).  B: reflectors also applied
+// to B's nrhs columns (solve).
+template <class S, bool PIVOT>
+__device__ void factor(const Lds &s, double *A, double *Tsave, double *scratch, int N, double *B, int nrhs) {
+  constexpr int NB = S::NB, LDV = S::LDV;
+  for (int c0 = 0; c0 < N; c0 += NB) {
+    const int w = min(NB, N - c0), m = N - c0, mr = round16(m);
+    if (PIVOT) select_panel<S>(s, A, scratch, N, c0, w);
+    for (int e = threadIdx.x; e < mr * NB; e += QT) {
+      const int r = e / NB, q = e % NB;
+      s.V[r * LDV + q] = (r < m && q < w) ? A[(long)(c0 + r) * N + c0 + q] : 0.0;
+    }
+    __syncthreads();
+    panel_factor<S>(s, m, w);
+    panel_store_clean<S>(s, A, N, c0, m, w, mr);
+    build_T<S>(s, m, w);
+    for (int e = threadIdx.x; e < NB * NB; e += QT) Tsave[(long)(c0 / NB) * NB * NB + e] = s.T[e];
+    if (c0 + w < N) apply_block<S, true, PIVOT>(s, A, N, c0, m, mr, c0 + w, N, w);
+    if (B) apply_block<S, true, false>(s, B, nrhs, c0, m, mr, 0, nrhs, 0);
+  }
+}
+
+template <class S>
+__global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long tstride, double *Sall,
+                                               double *Uall, double *Dall, double *RPall, int N) {
+  extern __shared__ double smem[];
+  const Lds s = carve<S>((char *)smem, N);
+  const long NN = (long)N * N, b = blockIdx.x;
+  double *X = Xall + b * NN, *U = Uall + b * NN, *RP = RPall + b * NN, *D = Dall + b * N;
+  double *Ts = Tall + b * tstride, *scr = Sall + b * (long)N * 32;
+  const int t = threadIdx.x;
+  for (int q = t; q < N; q += QT) {
+    double acc = 0.0;
+    for (int r = 0; r < N; ++r) { const double x = X[(long)r * N + q]; acc += x * x; }
+    s.norms[q] = acc;
+    s.orig[q] = q;
+  }
+  __syncthreads();
+  factor<S, true>(s, X, Ts, scr, N, nullptr, 0);
+  // D = diag R,  RP[i][orig[q]] = R[i][q] / R[i][i]
+  for (int i = t; i < N; i += QT) D[i] = X[(long)i * N + i];
+  for (long e = t; e < NN; e += QT) {
+    const int i = (int)(e / N), q = (int)(e % N);
+    const double v = q < i ? 0.0 : (q == i ? 1.0 : X[e] / X[(long)i * N + i]);
+    RP[(long)i * N + s.orig[q]] = v;
+  }
+  // Q = Q_0 Q_1 ... applied in reverse order to the identity
+  for (long e = t; e < NN; e += QT) U[e] = ((e / N) == (e % N)) ? 1.0 : 0.0;
+  __syncthreads();
+  const int np = (N + S::NB - 1) / S::NB;
+  for (int p = np - 1; p >= 0; --p) {
+    const int c0 = p * S::NB, w = min(S::NB, N - c0), m = N - c0, mr = round16(m);
+    panel_load_clean<S>(s, X, N, c0, m, w, mr);
+    for (int e = t; e < S::NB * S::NB; e += QT) s.T[e] = Ts[(long)p * S::NB * S::NB + e];
+    __syncthreads();
+    apply_block<S, false, false>(s, U, N, c0, m, mr, c0, N, 0);
+  }
+}
+
+template <class S>
+__global__ __launch_bounds__(QT) void k_qr_solve(double *Mall, double *Ball, double *Tall, long tstride, int N) {
+  constexpr int NB = S::NB;
+  extern __shared__ double smem[];
+  const Lds s = carve<S>((char *)smem, N);
+  const long NN = (long)N * N, b = blockIdx.x;
+  double *M = Mall + b * NN, *B = Ball + b * NN;
+  double *Ts = Tall + b * tstride;
+  factor<S, false>(s, M, Ts, nullptr, N, B, N);
+  // back substitution R Z = Y (Y = Q^T B in B), block rows from the bottom
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int np = (N + NB - 1) / NB;
+  double *Rd = s.T;   // diagonal block of R, [NB][NB]
+  for (int p = np - 1; p >= 0; --p) {
+    const int r0 = p * NB, w = min(NB, N - r0), k0 = r0 + w, kn = N - k0;
+    if (kn > 0) {   // Y_p -= R[r0:r0+w, k0:N] Z[k0:N, :]
+      const int ctiles = (N + 15) / 16;
+      for (int tile = wv; tile < (NB / 16) * ctiles; tile += 4) {
+        const int tr = tile / ctiles, tc = tile % ctiles;
+        M64::acc_t acc = {0, 0, 0, 0};
+        const int ri = r0 + tr * 16 + (lane & 15);
+        const int cj = tc * 16 + (lane & 15);
+        for (int kk = 0; kk < kn; kk += 4) {
+          const int k = k0 + kk + (lane >> 4);
+          const double a = (ri < r0 + w && k < N) ? M[(long)ri * N + k] : 0.0;
+          const double bb = (k < N && cj < N) ? B[(long)k * N + cj] : 0.0;
+          acc = M64::mac(a, bb, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = r0 + tr * 16 + M64::row(lane, r);
+          if (row < r0 + w && cj < N) B[(long)row * N + cj] -= acc[r];
+        }
+      }
+    }
+    for (int e = t; e < NB * NB; e += QT) {
+      const int i = e / NB, q = e % NB;
+      Rd[e] = (i < w && q < w) ? M[(long)(r0 + i) * N + r0 + q] : 0.0;
+    }
+    __syncthreads();
+    for (int q = t; q < N; q += QT) {   // one right-hand side column per thread
+      double z[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) z[i] = (i < w) ? B[(long)(r0 + i) * N + q] : 0.0;
+#pragma unroll
+      for (int i = NB - 1; i >= 0; --i) {
+        if (i < w) {
+          double acc = z[i];
+#pragma unroll
+          for (int k = i + 1; k < NB; ++k) acc -= Rd[i * NB + k] * z[k];
+          z[i] = acc / Rd[i * NB + i];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        if (i < w) B[(long)(r0 + i) * N + q] = z[i];
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int SMALL_MAX_N = 256;
+}  // namespace
+
+size_t qr_tsave_doubles(int N) {
+  const int nb = N <= SMALL_MAX_N ? ShapeS::NB : ShapeL::NB;
+  return (size_t)((N + nb - 1) / nb) * nb * nb;
+}
+
+size_t qr_scratch_doubles(int N) { return (size_t)N * 32; }
+
+hipError_t qr_udv_blocked(double *X, double *Scr, double *Tsave, double *U, double *D, double *RP, int mats, int N,
+                          hipStream_t s) {
+  if (N > 512) return hipErrorInvalidValue;
+  const long ts = (long)qr_tsave_doubles(N);
+  if (N <= SMALL_MAX_N)
+    hipLaunchKernelGGL(k_qr_udv<ShapeS>, dim3(mats), dim3(QT), lds_bytes<ShapeS>(N), s, X, Tsave, ts, Scr, U, D, RP,
+                       N);
+  else
+    hipLaunchKernelGGL(k_qr_udv<ShapeL>, dim3(mats), dim3(QT), lds_bytes<ShapeL>(N), s, X, Tsave, ts, Scr, U, D, RP,
+                       N);
+  return hipGetLastError();
+}
+
+hipError_t qr_solve_blocked(double *M, double *B, double *Tsave, int mats, int N, hipStream_t s) {
+  if (N > 512) return hipErrorInvalidValue;
+  const long ts = (long)qr_tsave_doubles(N);
+  if (N <= SMALL_MAX_N)
+    hipLaunchKernelGGL(k_qr_solve<ShapeS>, dim3(mats), dim3(QT), lds_bytes<ShapeS>(N), s, M, B, Tsave, ts, N);
+  else
+    hipLaunchKernelGGL(k_qr_solve<ShapeL>, dim3(mats), dim3(QT), lds_bytes<ShapeL>(N), s, M, B, Tsave, ts, N);
+  return hipGetLastError();
+}
+
+}  // namespace bss

@@ -7,10 +7,40 @@ namespace bss {
 
 namespace {
 
-// e^{-+dtau K} by plane waves: K is diagonalised by the lattice Fourier modes
-// with eigenvalues eps_k = -2t(cos kx + cos ky), so
-//   (e^{s K})_ij = (1/N) sum_k cos(k.(r_i - r_j)) e^{s eps_k}.
-// Phases are reduced modulo L in integers before the cosine.
+// e^{-+dtau K} in closed form.  The hopping of eq. (1) on the periodic
+// square lattice is K = -t (A_x + A_y) with commuting ring adjacencies, so
+//   (e^{-s K})_ij = r(dx) r(dy),   r(d) = sum_w (sgn)^{n} I_n(2 s t),  n = |d + w L|,
+// a sum over the periodic images of the one-dimensional free propagator
+// (I_n: modified Bessel function of the first kind; sgn = +1 for e^{-dtau K},
+// -1 for e^{+dtau K}).  Every term has the same sign for even L, so even the
+// smallest entries (~1e-24 at 16 x 16) come out to full relative precision,
+// which a plane-wave sum (absolute error ~1e-15) cannot give.
+__device__ double bessel_i(int n, double x) {
+  const double h = 0.5 * x;
+  double term = 1.0;
+  for (int j = 1; j <= n; ++j) term *= h / j;
+  double sum = 0.0;
+  for (int k = 0; k < 200 && term > 0.0; ++k) {
+    sum += term;
+    if (term < 1e-18 * sum) break;
+    term *= h * h / ((double)(k + 1) * (double)(n + k + 1));
+  }
+  return sum;
+}
+
+__device__ double ring_propagator(int d, int L, double x, bool alternate) {
+  double sum = 0.0;
+  for (int w = 0; w <= 64; ++w) {
+    double part = 0.0;
+    const int np = d + w * L, nm = w > 0 ? (w * L - d) : -1;   // images +w and -w
+    if (np <= 400) part += ((alternate && (np & 1)) ? -1.0 : 1.0) * bessel_i(np, x);
+    if (nm >= 0 && nm <= 400) part += ((alternate && (nm & 1)) ? -1.0 : 1.0) * bessel_i(nm, x);
+    sum += part;
+    if (w > 0 && fabs(part) <= 1e-18 * fabs(sum)) break;
+  }
+  return sum;
+}
+
 template <typename T>
 __global__ void k_build_exp(int L, double t, double dtau, double *Em, double *Ep, T *Etm, T *Etp) {
   const int N = L * L;
@@ -18,16 +48,9 @@ __global__ void k_build_exp(int L, double t, double dtau, double *Em, double *Ep
   if (e >= (long)N * N) return;
   const int i = (int)(e / N), j = (int)(e % N);
   const int dx = ((i % L) - (j % L) + L) % L, dy = ((i / L) - (j / L) + L) % L;
-  double sm = 0.0, sp = 0.0;
-  for (int my = 0; my < L; ++my)
-    for (int mx = 0; mx < L; ++mx) {
-      const double eps = -2.0 * t * (cospi(2.0 * mx / L) + cospi(2.0 * my / L));
-      const double ph = cospi(2.0 * ((mx * dx + my * dy) % L) / L);
-      sm += ph * exp(-dtau * eps);
-      sp += ph * exp(dtau * eps);
-    }
-  sm /= N;
-  sp /= N;
+  const double x = 2.0 * dtau * t;
+  const double sm = ring_propagator(dx, L, x, false) * ring_propagator(dy, L, x, false);
+  const double sp = ring_propagator(dx, L, x, true) * ring_propagator(dy, L, x, true);
   Em[e] = sm;
   Ep[e] = sp;
   if (Etm) { Etm[e] = (T)sm; Etp[e] = (T)sp; }

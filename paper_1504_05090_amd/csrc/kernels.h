@@ -33,6 +33,7 @@ struct ChainStats {
 // Flip phase of one slice for every chain of one instance.
 struct FlipArgs {
   int N, Lam, l, k, chains;
+  int fb;               // rows of X staged per flush block (set by the launcher)
   void *G;              // [2*chains][N][N] bulk type
   int8_t *h;            // [chains][Lam][N]
   void *dv;             // out: [2*chains][2][N] bulk type: D_l and D_l^{-1}
@@ -69,6 +70,14 @@ hipError_t bump_counter(int64_t *ctr, hipStream_t s);
 // Pre-pivoted Householder QR of X (overwritten): U = Q, D = diag(R),
 // RP = D^{-1} R Pi^T (so that X = U diag(D) RP).
 hipError_t qr_udv(double *X, double *U, double *D, double *RP, int mats, int N, hipStream_t s);
+// Blocked variants (compact WY, MFMA trailing updates).  Tsave holds
+// qr_tsave_doubles(N) and Scr qr_scratch_doubles(N) doubles per matrix; the
+// input X of qr_udv_blocked is overwritten.
+size_t qr_tsave_doubles(int N);
+size_t qr_scratch_doubles(int N);
+hipError_t qr_udv_blocked(double *X, double *Scr, double *Tsave, double *U, double *D, double *RP, int mats, int N,
+                          hipStream_t s);
+hipError_t qr_solve_blocked(double *M, double *B, double *Tsave, int mats, int N, hipStream_t s);
 // M Z = B by Householder QR (M overwritten, B replaced by Z).
 hipError_t qr_solve(double *M, double *B, int mats, int N, hipStream_t s);
 // Middle matrix of the two-sided fresh-G formula and its right-hand side.

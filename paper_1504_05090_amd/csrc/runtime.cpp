@@ -51,6 +51,8 @@ struct Inst {
   double *RU = nullptr, *RD = nullptr, *RV = nullptr;   // right chain after block b: [nb][...]
   double *LU = nullptr, *LD = nullptr, *LV = nullptr;   // left factors, entry b: (B_Lam..B_{l_b+1})^T
   double *W1 = nullptr, *W2 = nullptr, *W3 = nullptr, *Gf = nullptr, *Gt = nullptr, *invb = nullptr;
+  double *Tq = nullptr;                  // compact-WY T factors of the blocked QR
+  double *Sq = nullptr;                  // column-swap scratch of the blocked QR
   ChainStats *stats = nullptr;
   int64_t *sweep_ctr = nullptr, *trace_base = nullptr;
   uint8_t *trace = nullptr;
@@ -190,6 +192,8 @@ void layout(Inst &I, bool fp64, Carver &cv, int64_t trace_sweeps, bool tracing) 
   I.Gf = cv.take<double>(M * NN);
   I.Gt = cv.take<double>(M * NN);
   I.invb = cv.take<double>(M * I.N);
+  I.Tq = cv.take<double>(M * qr_tsave_doubles(I.N));
+  I.Sq = cv.take<double>(M * qr_scratch_doubles(I.N));
   I.stats = cv.take<ChainStats>(I.C);
   I.sweep_ctr = cv.take<int64_t>(1);
   I.trace_base = cv.take<int64_t>(1);
@@ -305,7 +309,7 @@ struct Exec {
     gemm64(A, ta, Ui, false, I.W1, (long)NN(), (long)NN(), nullptr, 0, Di, I.N);
     {
       Timed tm(c, F_QR_UDV, s);
-      chk(qr_udv(I.W1, Uo, Do, I.W2, I.mats, I.N, s));
+      chk(qr_udv_blocked(I.W1, I.Sq, I.Tq, Uo, Do, I.W2, I.mats, I.N, s));
     }
     gemm64(I.W2, false, Vi, false, Vo, (long)NN(), (long)NN());
   }
@@ -325,7 +329,7 @@ struct Exec {
       chk(fresh_prep(RU(b), RD(b), RV(b), I.W1, nullptr, nullptr, I.W3, I.mats, I.N, s));
     }
     if (rhs_v) { Timed tm(c, F_ELEM, s); chk(time_rhs(RD(b), RV(b), I.W3, I.mats, I.N, s)); }
-    { Timed tm(c, F_QR_SOLVE, s); chk(qr_solve(I.W1, I.W3, I.mats, I.N, s)); }
+    { Timed tm(c, F_QR_SOLVE, s); chk(qr_solve_blocked(I.W1, I.W3, I.Tq, I.mats, I.N, s)); }
     if (left) {
       { Timed tm(c, F_ELEM, s); chk(inv_big(LD(b), I.invb, (long)I.mats * I.N, s)); }
       gemm64(LU(b), false, I.W3, false, out, (long)NN(), (long)NN(), I.invb, I.N);
