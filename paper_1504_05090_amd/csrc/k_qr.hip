@@ -26,6 +26,24 @@ namespace {
 constexpr int QT = 256;   // 4 wavefronts
 typedef Mfma<double> M64;
 
+#ifdef BSS_QR_TIMING
+// phase timers of workgroup 0 (diagnostic builds only)
+__device__ unsigned long long qr_phase_ticks[16];
+#define QR_TICK(id)                                                          \
+  do {                                                                       \
+    __syncthreads();                                                         \
+    if (blockIdx.x == 0 && threadIdx.x == 0) {                               \
+      const unsigned long long now_ = clock64();                             \
+      qr_phase_ticks[id] += now_ - qr_tick_last;                             \
+      qr_tick_last = now_;                                                   \
+    }                                                                        \
+  } while (0)
+#define QR_TICK_INIT unsigned long long qr_tick_last = clock64()
+#else
+#define QR_TICK(id) do {} while (0)
+#define QR_TICK_INIT do {} while (0)
+#endif
+
 // per-shape constants: panel width NB, chunk width CW, max row tiles per wave
 template <int NB_, int CW_, int RTW_> struct Shape {
   static constexpr int NB = NB_, CW = CW_, RTW = RTW_;
@@ -44,10 +62,12 @@ struct Lds {
   double *tau;    // [NB]
   double *beta;   // [NB]
   double *red;    // [64]
+  double *pn;     // [NB] in-panel pivot norms (rows >= j)
+  double *pg;     // [NB] (rows > j)
   double *norms;  // [N]  current column norms (udv)
   double *npart;  // [4][CW] per-wave partial norms (aliases the spare partials of Wp)
   int *orig;      // [N]  original index of each physical column (udv)
-  int *sel;       // [N]  scratch for the panel selection
+  int *sel;       // [N + 3 NB + 1] scratch for the panel selection
 };
 
 __device__ __forceinline__ int round16(int x) { return (x + 15) & ~15; }
@@ -64,6 +84,8 @@ __device__ Lds carve(char *base, int N) {
   s.tau = p; p += S::NB;
   s.beta = p; p += S::NB;
   s.red = p; p += 64;
+  s.pn = p; p += S::NB;
+  s.pg = p; p += S::NB;
   s.norms = p; p += N;
   s.npart = s.Wp + S::NB * S::CW;   // partial 1..3 of Wp are free once W is summed
   s.orig = (int *)p;
@@ -74,20 +96,54 @@ __device__ Lds carve(char *base, int N) {
 template <class S>
 size_t lds_bytes(int N) {
   const int mr = (N + 15) & ~15;
-  const size_t d = (size_t)mr * S::LDV + 4 * S::NB * S::CW + S::NB * S::CW + S::NB * S::NB + 2 * S::NB + 64 + N;
-  return d * sizeof(double) + 2 * sizeof(int) * N;
+  const size_t d = (size_t)mr * S::LDV + 4 * S::NB * S::CW + S::NB * S::CW + S::NB * S::NB + 4 * S::NB + 64 + N;
+  return d * sizeof(double) + sizeof(int) * (2 * N + 3 * S::NB + 1);
 }
 
 // Unblocked Householder on the LDS panel V[0..m) x [0..w): on return the
 // strict lower part holds v (v_j = 1 implicit), beta[j] = R_jj, tau[j].
-template <class S>
-__device__ void panel_factor(const Lds &s, int m, int w) {
+// Eight threads own each column.  With PIVOT the panel's columns are also
+// pivoted (largest remaining norm first, Businger-Golub within the panel);
+// the owners recompute their column's norm while applying each reflector,
+// and the swaps are recorded in swp[j] for the rows above the panel.
+template <class S, bool PIVOT>
+__device__ void panel_factor(const Lds &s, int m, int w, int *swp) {
   constexpr int LDV = S::LDV;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, sub = t & 7, qo = t >> 3;
+  // pn[q]: norm^2 of column q over rows >= j; pg[q]: over rows > j
+  {
+    const int q = qo;
+    double a0 = 0.0, a1 = 0.0;
+    if (q < w)
+      for (int r = sub; r < m; r += 8) { const double x = s.V[r * LDV + q]; a0 += x * x; if (r > 0) a1 += x * x; }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) { a0 += __shfl_xor(a0, o, 64); a1 += __shfl_xor(a1, o, 64); }
+    if (q < w && sub == 0) { s.pn[q] = a0; s.pg[q] = a1; }
+    __syncthreads();
+  }
   for (int j = 0; j < w; ++j) {
-    double part = 0.0;
-    for (int r = j + 1 + t; r < m; r += QT) { const double x = s.V[r * LDV + j]; part += x * x; }
-    const double xn2 = block_sum(part, s.red);
+    if (PIVOT) {
+      int p = j;
+      double best = s.pn[j];
+      for (int q = j + 1; q < w; ++q)
+        if (s.pn[q] > best) { best = s.pn[q]; p = q; }
+      __syncthreads();   // every thread has read pn before thread 0 permutes it
+      if (p != j) {
+        for (int r = t; r < m; r += QT) {
+          const double a = s.V[r * LDV + j];
+          s.V[r * LDV + j] = s.V[r * LDV + p];
+          s.V[r * LDV + p] = a;
+        }
+      }
+      if (t == 0) {
+        swp[j] = p;
+        const double a = s.pn[j], b = s.pg[j];
+        s.pn[j] = s.pn[p]; s.pg[j] = s.pg[p];
+        s.pn[p] = a; s.pg[p] = b;
+      }
+      __syncthreads();
+    }
+    const double xn2 = s.pg[j];
     const double x0 = s.V[j * LDV + j];
     double tj = 0.0, bj = x0, scale = 0.0;
     if (xn2 > 0.0) {
@@ -95,26 +151,28 @@ __device__ void panel_factor(const Lds &s, int m, int w) {
       tj = (bj - x0) / bj;
       scale = 1.0 / (x0 - bj);
     }
-    __syncthreads();
     for (int r = j + 1 + t; r < m; r += QT) s.V[r * LDV + j] *= scale;
     if (t == 0) { s.tau[j] = tj; s.beta[j] = bj; }
     __syncthreads();
-    if (tj != 0.0) {   // columns q > j of the panel, 8 threads per column
-      const int q = j + 1 + (t >> 3), sub = t & 7;
-      double acc = 0.0;
-      if (q < w) {
-        acc = (sub == 0) ? s.V[j * LDV + q] : 0.0;
-        for (int r = j + 1 + sub; r < m; r += 8) acc += s.V[r * LDV + j] * s.V[r * LDV + q];
-      }
+    const int q = j + 1 + qo;
+    double a1 = 0.0, head = 0.0;   // norms of column q over rows > j+1 and its row j+1
+    if (q < w) {
+      double acc = (sub == 0) ? s.V[j * LDV + q] : 0.0;
+      for (int r = j + 1 + sub; r < m; r += 8) acc += s.V[r * LDV + j] * s.V[r * LDV + q];
       acc += __shfl_xor(acc, 1, 64);
       acc += __shfl_xor(acc, 2, 64);
       acc += __shfl_xor(acc, 4, 64);
-      if (q < w) {
-        const double f = tj * acc;
-        if (sub == 0) s.V[j * LDV + q] -= f;
-        for (int r = j + 1 + sub; r < m; r += 8) s.V[r * LDV + q] -= f * s.V[r * LDV + j];
+      const double f = tj * acc;
+      if (sub == 0) s.V[j * LDV + q] -= f;
+      for (int r = j + 1 + sub; r < m; r += 8) {
+        const double v = s.V[r * LDV + q] - f * s.V[r * LDV + j];
+        s.V[r * LDV + q] = v;
+        if (r > j + 1) a1 += v * v; else head = v;
       }
     }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) { a1 += __shfl_xor(a1, o, 64); head += __shfl_xor(head, o, 64); }
+    if (q < w && sub == 0) { s.pg[q] = a1; s.pn[q] = a1 + head * head; }
     __syncthreads();
   }
 }
@@ -151,17 +209,40 @@ __device__ void panel_load_clean(const Lds &s, const double *A, int N, int c0, i
 
 // T (upper triangular) of Q_p = I - V T V^T:
 // T_jj = tau_j,  T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j).
+// The Gram matrix V^T V comes from FP64 MFMA (K split over the wavefronts).
 template <class S>
-__device__ void build_T(const Lds &s, int m, int w) {
-  constexpr int LDV = S::LDV, NB = S::NB;
-  const int t = threadIdx.x;
-  double *gram = s.Wp;
+__device__ void build_T(const Lds &s, int m, int w, int mr) {
+  constexpr int LDV = S::LDV, NB = S::NB, WT = S::WT;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, l16 = lane & 15, lq = lane >> 4;
+  double *part = s.Wp;                    // [4][NB][NB] partial Gram matrices
+  double *gram = s.Wp + 4 * NB * NB;      // [NB][NB]
+  {
+    const int kq = mr / 4, kb = wv * kq;
+    M64::acc_t g[WT][WT];
+#pragma unroll
+    for (int a = 0; a < WT; ++a)
+#pragma unroll
+      for (int b = 0; b < WT; ++b) g[a][b] = M64::acc_t{0, 0, 0, 0};
+    for (int k0 = kb; k0 < kb + kq; k0 += 4) {
+      const int k = k0 + lq;
+      double va[WT];
+#pragma unroll
+      for (int a = 0; a < WT; ++a) va[a] = s.V[k * LDV + 16 * a + l16];
+#pragma unroll
+      for (int a = 0; a < WT; ++a)
+#pragma unroll
+        for (int b = 0; b < WT; ++b) g[a][b] = M64::mac(va[a], va[b], g[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < WT; ++a)
+#pragma unroll
+      for (int b = 0; b < WT; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[(wv * NB + 16 * a + M64::row(lane, r)) * NB + 16 * b + l16] = g[a][b][r];
+  }
+  __syncthreads();
   for (int e = t; e < NB * NB; e += QT) {
-    const int i = e / NB, j = e % NB;
-    double acc = 0.0;
-    if (i < j && j < w)
-      for (int r = j; r < m; ++r) acc += s.V[r * LDV + i] * s.V[r * LDV + j];
-    gram[e] = acc;
+    gram[e] = (part[e] + part[NB * NB + e]) + (part[2 * NB * NB + e] + part[3 * NB * NB + e]);
     s.T[e] = 0.0;
   }
   __syncthreads();
@@ -174,6 +255,7 @@ __device__ void build_T(const Lds &s, int m, int w) {
     if (t == 0) s.T[j * NB + j] = s.tau[j];
     __syncthreads();
   }
+  (void)m;
 }
 
 // Apply (I - V op(T) V^T) to columns [c0, c1) of X (rows r0..r0+m), row
@@ -292,63 +374,74 @@ __device__ void apply_block(const Lds &s, double *X, long ldx, int r0, int m, in
 }
 
 // Swap the NB remaining columns of largest current norm (ties: lower physical
-// index first) into positions [c0, c0 + w), in order of decreasing norm.
+// index first) into positions [c0, c0 + w), in order of decreasing norm; the
+// columns they displace take the vacated positions (k-th displaced column,
+// by position, to the k-th vacated position).  Whole columns move, so the R
+// rows above the panel stay consistent; the chosen columns are staged in the
+// (still free) panel area of LDS.
 template <class S>
-__device__ void select_panel(const Lds &s, double *A, double *scratch, int N, int c0, int w) {
+__device__ void select_panel(const Lds &s, double *A, int N, int c0, int w) {
+  constexpr int LDV = S::LDV;
   const int t = threadIdx.x;
-  // rank among the remaining columns
+  int *rank = s.sel;          // [N]
+  int *src = s.sel + N;       // [NB]  chosen column of each rank
+  int *mv_from = src + S::NB; // [NB]  displaced column positions
+  int *mv_to = mv_from + S::NB;
+  int *nmv = mv_to + S::NB;
+  // a NaN norm ranks last, so that the comparison stays a strict total order
+  // and the ranks of the remaining columns are a permutation of 0..N-c0-1
   for (int q = c0 + t; q < N; q += QT) {
-    const double nq = s.norms[q];
-    int rank = 0;
-    for (int p = c0; p < N; ++p) rank += (s.norms[p] > nq) || (s.norms[p] == nq && p < q);
-    s.sel[q] = rank;
-  }
-  __syncthreads();
-  // chosen column with rank r goes to position c0 + r; the displaced columns
-  // (not chosen, sitting in [c0, c0+w)) fill the vacated positions in order
-  if (t == 0) {
-    int nd = 0;
-    // reuse orig-like bookkeeping in the sel array beyond N is not available:
-    // build the move list sequentially (w <= 32 entries)
-    int src[32], dst[32];
-    int vac[32], nv = 0, dis[32];
-    for (int q = c0; q < N; ++q) {
-      const int r = s.sel[q];
-      if (r < w) { src[r] = q; if (q >= c0 + w) vac[nv++] = q; }
+    const double nq = isnan(s.norms[q]) ? -1.0 : s.norms[q];
+    int r = 0;
+    for (int p = c0; p < N; ++p) {
+      const double np_ = isnan(s.norms[p]) ? -1.0 : s.norms[p];
+      r += (np_ > nq) || (np_ == nq && p < q);
     }
-    for (int q = c0; q < c0 + w; ++q)
-      if (s.sel[q] >= w) dis[nd++] = q;
-    // encode moves into sel[0..2w): sel[i] = from, sel[w + i] = to
-    for (int r = 0; r < w; ++r) { s.sel[r] = src[r]; s.sel[w + r] = c0 + r; }
-    for (int i = 0; i < nd; ++i) { s.sel[2 * w + i] = dis[i]; s.sel[3 * w + i] = vac[i]; }
-    s.sel[4 * w] = nd;
+    rank[q] = r;
   }
   __syncthreads();
-  const int nd = s.sel[4 * w];
-  // copy the chosen columns out (all rows), then move displaced ones, then write back
+  for (int q = c0 + t; q < N; q += QT) {
+    const int r = rank[q];
+    if (r < w) src[r] = q;
+    if (r < w && q >= c0 + w) {          // vacated position: k-th among them
+      int k = 0;
+      for (int p = c0 + w; p < q; ++p) k += rank[p] < w;
+      mv_to[k] = q;
+    }
+    if (r >= w && q < c0 + w) {          // displaced column: k-th among them
+      int k = 0;
+      for (int p = c0; p < q; ++p) k += rank[p] >= w;
+      mv_from[k] = q;
+    }
+  }
+  if (t == 0) {
+    int k = 0;
+    for (int p = c0; p < c0 + w; ++p) k += rank[p] >= w;
+    *nmv = k;
+  }
+  __syncthreads();
+  const int nd = min(*nmv, w);
+  // stage chosen columns (all rows), move the displaced ones, write back
   for (int e = t; e < N * w; e += QT) {
     const int r = e / w, i = e % w;
-    scratch[(long)r * 32 + i] = A[(long)r * N + s.sel[i]];
+    s.V[r * LDV + i] = A[(long)r * N + src[i]];
   }
+  int o_i = 0, o_d = 0;
+  double n_i = 0.0, n_d = 0.0;
+  if (t < w) { o_i = s.orig[src[t]]; n_i = s.norms[src[t]]; }
+  if (t < nd) { o_d = s.orig[mv_from[t]]; n_d = s.norms[mv_from[t]]; }
   __syncthreads();
   for (int e = t; e < N * nd; e += QT) {
     const int r = e / nd, i = e % nd;
-    A[(long)r * N + s.sel[3 * w + i]] = A[(long)r * N + s.sel[2 * w + i]];
+    A[(long)r * N + mv_to[i]] = A[(long)r * N + mv_from[i]];
   }
+  if (t < nd) { s.orig[mv_to[t]] = o_d; s.norms[mv_to[t]] = n_d; }
   __syncthreads();
   for (int e = t; e < N * w; e += QT) {
     const int r = e / w, i = e % w;
-    A[(long)r * N + c0 + i] = scratch[(long)r * 32 + i];
+    A[(long)r * N + c0 + i] = s.V[r * LDV + i];
   }
-  // bookkeeping of original indices and norms (single thread, w <= 32 moves)
-  if (t == 0) {
-    int o_src[32], o_dis[32];
-    double n_src[32], n_dis[32];
-    for (int i = 0; i < w; ++i) { o_src[i] = s.orig[s.sel[i]]; n_src[i] = s.norms[s.sel[i]]; }
-    for (int i = 0; i < nd; ++i) { o_dis[i] = s.orig[s.sel[2 * w + i]]; n_dis[i] = s.norms[s.sel[2 * w + i]]; }
-    for (int i = 0; i < nd; ++i) { s.orig[s.sel[3 * w + i]] = o_dis[i]; s.norms[s.sel[3 * w + i]] = n_dis[i]; }
-    for (int i = 0; i < w; ++i) { s.orig[c0 + i] = o_src[i]; s.norms[c0 + i] = n_src[i]; }
-  }
+  if (t < w) { s.orig[c0 + t] = o_i; s.norms[c0 + t] = n_i; }
   __syncthreads();
 }
 
@@ -358,20 +451,46 @@ __device__ void select_panel(const Lds &s, double *A, double *scratch, int N, in
 template <class S, bool PIVOT>
 __device__ void factor(const Lds &s, double *A, double *Tsave, double *scratch, int N, double *B, int nrhs) {
   constexpr int NB = S::NB, LDV = S::LDV;
+  QR_TICK_INIT;
   for (int c0 = 0; c0 < N; c0 += NB) {
     const int w = min(NB, N - c0), m = N - c0, mr = round16(m);
-    if (PIVOT) select_panel<S>(s, A, scratch, N, c0, w);
+    if (PIVOT) select_panel<S>(s, A, N, c0, w);
+    QR_TICK(0);
     for (int e = threadIdx.x; e < mr * NB; e += QT) {
       const int r = e / NB, q = e % NB;
       s.V[r * LDV + q] = (r < m && q < w) ? A[(long)(c0 + r) * N + c0 + q] : 0.0;
     }
     __syncthreads();
-    panel_factor<S>(s, m, w);
+    QR_TICK(1);
+    panel_factor<S, PIVOT>(s, m, w, s.sel);
+    if (PIVOT) {
+      // the in-panel swaps also permute the R rows above the panel and orig[]
+      for (int r = threadIdx.x; r < c0; r += QT)
+        for (int j = 0; j < w; ++j) {
+          const int p = s.sel[j];
+          if (p != j) {
+            const double a = A[(long)r * N + c0 + j];
+            A[(long)r * N + c0 + j] = A[(long)r * N + c0 + p];
+            A[(long)r * N + c0 + p] = a;
+          }
+        }
+      if (threadIdx.x == 0)
+        for (int j = 0; j < w; ++j) {
+          const int p = s.sel[j];
+          if (p != j) { const int a = s.orig[c0 + j]; s.orig[c0 + j] = s.orig[c0 + p]; s.orig[c0 + p] = a; }
+        }
+      __syncthreads();
+    }
+    QR_TICK(2);
     panel_store_clean<S>(s, A, N, c0, m, w, mr);
-    build_T<S>(s, m, w);
+    QR_TICK(3);
+    build_T<S>(s, m, w, mr);
     for (int e = threadIdx.x; e < NB * NB; e += QT) Tsave[(long)(c0 / NB) * NB * NB + e] = s.T[e];
+    QR_TICK(4);
     if (c0 + w < N) apply_block<S, true, PIVOT>(s, A, N, c0, m, mr, c0 + w, N, w);
+    QR_TICK(5);
     if (B) apply_block<S, true, false>(s, B, nrhs, c0, m, mr, 0, nrhs, 0);
+    QR_TICK(6);
   }
 }
 
@@ -384,13 +503,17 @@ __global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long 
   double *X = Xall + b * NN, *U = Uall + b * NN, *RP = RPall + b * NN, *D = Dall + b * N;
   double *Ts = Tall + b * tstride, *scr = Sall + b * (long)N * 32;
   const int t = threadIdx.x;
-  for (int q = t; q < N; q += QT) {
-    double acc = 0.0;
-    for (int r = 0; r < N; ++r) { const double x = X[(long)r * N + q]; acc += x * x; }
-    s.norms[q] = acc;
-    s.orig[q] = q;
+  {
+    QR_TICK_INIT;
+    for (int q = t; q < N; q += QT) {
+      double acc = 0.0;
+      for (int r = 0; r < N; ++r) { const double x = X[(long)r * N + q]; acc += x * x; }
+      s.norms[q] = acc;
+      s.orig[q] = q;
+    }
+    __syncthreads();   // the panel selection reads every column's norm
+    QR_TICK(9);
   }
-  __syncthreads();
   factor<S, true>(s, X, Ts, scr, N, nullptr, 0);
   // D = diag R,  RP[i][orig[q]] = R[i][q] / R[i][i]
   for (int i = t; i < N; i += QT) D[i] = X[(long)i * N + i];
@@ -403,12 +526,15 @@ __global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long 
   for (long e = t; e < NN; e += QT) U[e] = ((e / N) == (e % N)) ? 1.0 : 0.0;
   __syncthreads();
   const int np = (N + S::NB - 1) / S::NB;
+  QR_TICK_INIT;
   for (int p = np - 1; p >= 0; --p) {
     const int c0 = p * S::NB, w = min(S::NB, N - c0), m = N - c0, mr = round16(m);
     panel_load_clean<S>(s, X, N, c0, m, w, mr);
     for (int e = t; e < S::NB * S::NB; e += QT) s.T[e] = Ts[(long)p * S::NB * S::NB + e];
     __syncthreads();
+    QR_TICK(7);
     apply_block<S, false, false>(s, U, N, c0, m, mr, c0, N, 0);
+    QR_TICK(8);
   }
 }
 
@@ -486,6 +612,7 @@ size_t qr_scratch_doubles(int N) { return (size_t)N * 32; }
 hipError_t qr_udv_blocked(double *X, double *Scr, double *Tsave, double *U, double *D, double *RP, int mats, int N,
                           hipStream_t s) {
   if (N > 512) return hipErrorInvalidValue;
+  if ((N <= SMALL_MAX_N ? lds_bytes<ShapeS>(N) : lds_bytes<ShapeL>(N)) > 160 * 1024) return hipErrorInvalidValue;
   const long ts = (long)qr_tsave_doubles(N);
   if (N <= SMALL_MAX_N)
     hipLaunchKernelGGL(k_qr_udv<ShapeS>, dim3(mats), dim3(QT), lds_bytes<ShapeS>(N), s, X, Tsave, ts, Scr, U, D, RP,
