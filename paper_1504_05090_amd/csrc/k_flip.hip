@@ -114,14 +114,14 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
   if (own && a.trace_mode != 0) {
     const int64_t rel = sweep - *a.trace_base;
     if (rel >= 0 && rel < a.trace_sweeps)
-      trace_idx = ((rel * a.chains + c) * (long)a.Lam + (a.l - 1)) * N + j;
+      trace_idx = ((rel * a.chains_total + a.chain0 + c) * (long)a.Lam + (a.l - 1)) * N + j;
   }
   if (own) {
     if (a.trace_mode == 2) {
       if (trace_idx >= 0) forced = a.trace[trace_idx] != 0;
       else atomicOr(a.err, 8);     // replay past the supplied history
     } else {
-      uj = uniform53(philox_word0((uint64_t)sweep, (uint64_t)(a.l - 1) * N + j, 0, 0, a.seed + (uint64_t)c, a.inst));
+      uj = uniform53(philox_word0((uint64_t)sweep, (uint64_t)(a.l - 1) * N + j, 0, 0, a.seed + (uint64_t)(a.chain0 + c), a.inst));
     }
   }
   T xs[2][KM], ys[2][KM];

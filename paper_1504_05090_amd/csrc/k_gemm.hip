@@ -1,23 +1,31 @@
-// Batched MFMA GEMM for gfx950 (FP32 and FP64, 16x16x4 matrix cores).
+// Batched MFMA GEMM for gfx950 (FP32 and FP64 on 16x16x4 matrix cores).
 //
-// Used by the wraps G <- e^{-dtau K} (D G D^{-1}) e^{+dtau K}, the FP64
-// block products of the B chain and the UDV / fresh-G products.  One
-// workgroup of 4 wavefronts computes a 64 x 64 output tile; each wavefront
-// owns a 32 x 32 quadrant (2 x 2 MFMA blocks).  K is staged through LDS in
-// chunks of 16.  Optional diagonal scalings (of A's columns, of the result's
-// rows and columns) are fused into the tile loads and the epilogue.
+// Used by the wraps G <- e^{-dtau K} (D G D^{-1}) e^{+dtau K}, the FP64 block
+// products of the B chain and the UDV / fresh-G products.  A workgroup of 4
+// wavefronts computes a BM x BN output tile; wavefront (wr, wc) owns a
+// WM x WN quadrant of (WM/16) x (WN/16) MFMA blocks.  K advances in chunks of
+// BK through a double-buffered LDS stage: the next chunk is fetched from
+// global memory into registers while the current one feeds the MFMAs, so a
+// chunk costs one barrier.  Operands are stored k-major in LDS so that the
+// 16 lanes of an MFMA operand read 16 consecutive words.  Optional diagonal
+// scalings (of A's columns, of the result's rows and columns) are fused into
+// the A fetch and the epilogue.
 #include "common.h"
 #include "kernels.h"
 
 namespace bss {
 
 namespace {
-constexpr int BM = 64, BN = 64, BK = 16;
 
-template <typename T, bool TA, bool TB>
+template <typename T, bool TA, bool TB, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
-  __shared__ T As[BM][BK + 1];
-  __shared__ T Bs[BK][BN + 1];
+  constexpr int WM = BM / 2, WN = BN / 2;          // 2 x 2 wavefronts
+  constexpr int TM = WM / 16, TN = WN / 16;        // MFMA blocks per wavefront
+  constexpr int PA = BM + 4, PB = BN + 4;          // padded LDS row lengths
+  constexpr int EA = BM * BK / 256, EB = BK * BN / 256;   // elements per thread per chunk
+  __shared__ T As[2][BK][PA];
+  __shared__ T Bs[2][BK][PB];
+
   const int tilesN = (d.N + BN - 1) / BN;
   const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
   const long b = blockIdx.y;
@@ -29,61 +37,96 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
   const T *cs = d.cs ? (const T *)d.cs + b * d.scs : nullptr;
   const int i0 = tm * BM, j0 = tn * BN;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, wr = w >> 1, wc = w & 1;
-  typedef typename Mfma<T>::acc_t acc_t;
-  acc_t acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int c = 0; c < 2; ++c) acc[a][c] = acc_t{0, 0, 0, 0};
+  const int l16 = lane & 15, lq = lane >> 4;
 
-  for (int k0 = 0; k0 < d.K; k0 += BK) {
+  // chunk element e of this thread -> (row, k) of A / (k, col) of B, chosen so
+  // that consecutive threads read consecutive global addresses
+  auto a_index = [&](int e, int &ii, int &kk) {
+    const int idx = e * 256 + t;
+    if (!TA) { ii = idx / BK; kk = idx % BK; } else { kk = idx / BM; ii = idx % BM; }
+  };
+  auto b_index = [&](int e, int &kk, int &jj) {
+    const int idx = e * 256 + t;
+    if (!TB) { kk = idx / BN; jj = idx % BN; } else { jj = idx / BK; kk = idx % BK; }
+  };
+  T ra[EA], rb[EB];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = t * 4 + e;
+    for (int e = 0; e < EA; ++e) {
       int ii, kk;
-      if (!TA) { ii = idx / BK; kk = idx % BK; } else { kk = idx / BM; ii = idx % BM; }
+      a_index(e, ii, kk);
       const int gi = i0 + ii, gk = k0 + kk;
       T v = 0;
       if (gi < d.M && gk < d.K) {
         v = TA ? A[(long)gk * d.lda + gi] : A[(long)gi * d.lda + gk];
         if (ks) v *= ks[gk];
       }
-      As[ii][kk] = v;
+      ra[e] = v;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = t * 4 + e;
-      int jj, kk;
-      if (!TB) { kk = idx / BN; jj = idx % BN; } else { jj = idx / BK; kk = idx % BK; }
+    for (int e = 0; e < EB; ++e) {
+      int kk, jj;
+      b_index(e, kk, jj);
       const int gj = j0 + jj, gk = k0 + kk;
       T v = 0;
       if (gj < d.N && gk < d.K) v = TB ? B[(long)gj * d.ldb + gk] : B[(long)gk * d.ldb + gj];
-      Bs[kk][jj] = v;
+      rb[e] = v;
     }
-    __syncthreads();
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      int ii, kk;
+      a_index(e, ii, kk);
+      As[buf][kk][ii] = ra[e];
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      int kk, jj;
+      b_index(e, kk, jj);
+      Bs[buf][kk][jj] = rb[e];
+    }
+  };
+
+  typedef typename Mfma<T>::acc_t acc_t;
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int c = 0; c < TN; ++c) acc[a][c] = acc_t{0, 0, 0, 0};
+
+  const int nk = (d.K + BK - 1) / BK;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int kc = 0; kc < nk; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nk) fetch((kc + 1) * BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      T av[2], bv[2];
+      T av[TM], bv[TN];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = As[wr * 32 + a * 16 + (lane & 15)][kk + (lane >> 4)];
+      for (int a = 0; a < TM; ++a) av[a] = As[buf][kk + lq][wr * WM + a * 16 + l16];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) bv[c] = Bs[kk + (lane >> 4)][wc * 32 + c * 16 + (lane & 15)];
+      for (int c = 0; c < TN; ++c) bv[c] = Bs[buf][kk + lq][wc * WN + c * 16 + l16];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < TM; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) acc[a][c] = Mfma<T>::mac(av[a], bv[c], acc[a][c]);
+        for (int c = 0; c < TN; ++c) acc[a][c] = Mfma<T>::mac(av[a], bv[c], acc[a][c]);
     }
+    if (kc + 1 < nk) stash(buf ^ 1);
     __syncthreads();
   }
+
   const T alpha = (T)d.alpha, beta = (T)d.beta;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < TN; ++c)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = i0 + wr * 32 + a * 16 + Mfma<T>::row(lane, r);
-        const int col = j0 + wc * 32 + c * 16 + (lane & 15);
+        const int row = i0 + wr * WM + a * 16 + Mfma<T>::row(lane, r);
+        const int col = j0 + wc * WN + c * 16 + l16;
         if (row < d.M && col < d.N) {
           T v = alpha * acc[a][c][r];
           if (rs) v *= rs[row];
@@ -95,16 +138,30 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
       }
 }
 
+template <typename T, int BM, int BN, int BK>
+void launch_shape(const GemmDesc &d, bool ta, bool tb, hipStream_t s) {
+  const int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
+  dim3 grid(tiles, d.batch), block(256);
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm<T, false, false, BM, BN, BK>), grid, block, 0, s, d);
+  else if (ta && !tb) hipLaunchKernelGGL((k_gemm<T, true, false, BM, BN, BK>), grid, block, 0, s, d);
+  else if (!ta && tb) hipLaunchKernelGGL((k_gemm<T, false, true, BM, BN, BK>), grid, block, 0, s, d);
+  else hipLaunchKernelGGL((k_gemm<T, true, true, BM, BN, BK>), grid, block, 0, s, d);
+}
+
 template <typename T>
 hipError_t launch(const GemmDesc &d, bool ta, bool tb, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   if (d.batch > 65535) return hipErrorInvalidValue;
-  const int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
-  dim3 grid(tiles, d.batch), block(256);
-  if (!ta && !tb) hipLaunchKernelGGL((k_gemm<T, false, false>), grid, block, 0, s, d);
-  else if (ta && !tb) hipLaunchKernelGGL((k_gemm<T, true, false>), grid, block, 0, s, d);
-  else if (!ta && tb) hipLaunchKernelGGL((k_gemm<T, false, true>), grid, block, 0, s, d);
-  else hipLaunchKernelGGL((k_gemm<T, true, true>), grid, block, 0, s, d);
+  // tile shapes measured on the batched 256^3 products: FP32 128 x 128 with
+  // 32-deep K chunks, FP64 64 x 128 with 16-deep chunks (fewer registers)
+  const bool big = d.M >= 192 && d.N >= 192;
+  if constexpr (sizeof(T) == 4) {
+    if (big) launch_shape<T, 128, 128, 32>(d, ta, tb, s);
+    else launch_shape<T, 64, 64, 32>(d, ta, tb, s);
+  } else {
+    if (big) launch_shape<T, 64, 128, 16>(d, ta, tb, s);
+    else launch_shape<T, 64, 64, 16>(d, ta, tb, s);
+  }
   return hipGetLastError();
 }
 }  // namespace

@@ -33,6 +33,7 @@ struct ChainStats {
 // Flip phase of one slice for every chain of one instance.
 struct FlipArgs {
   int N, Lam, l, k, chains;
+  int chain0, chains_total;   // first chain of this launch, chains of the instance
   int fb;               // rows of X staged per flush block (set by the launcher)
   void *G;              // [2*chains][N][N] bulk type
   int8_t *h;            // [chains][Lam][N]
@@ -43,7 +44,7 @@ struct FlipArgs {
   uint64_t seed, inst;
   const int64_t *sweep;        // device sweep counter
   int trace_mode;              // 0 none, 1 record, 2 replay
-  uint8_t *trace;              // [sweeps][chains][Lam][N]
+  uint8_t *trace;              // [sweeps][chains_total][Lam][N]
   const int64_t *trace_base;   // sweep index of trace entry 0
   int64_t trace_sweeps;        // capacity in sweeps
   ChainStats *stats;

@@ -1,11 +1,24 @@
 // Host runtime of the BSS-QMC sweep library: argument checking, device
 // memory layout, the per-slice launch schedule, stabilisation bookkeeping,
 // measurement, trace record/replay, checkpoints and the C ABI of bssqmc.h.
+//
+// Scheduling.  The chains of an instance are split into shards, contiguous
+// chain ranges with their own device state and their own pair of HIP streams
+// (main, aux).  The flip kernel of a slice occupies one CU per chain and is
+// latency bound, so the shards' launch sequences are interleaved slice by
+// slice and the hardware overlaps one shard's flips with another shard's
+// GEMMs and QRs.  The left-stack rebuild at the end of a sweep depends only on
+// that sweep's block products: it runs on the aux stream, and the next sweep
+// waits for it only at its first recomputation.  Every enqueuing call forks
+// from the context stream and joins back into it, so the caller sees a
+// single asynchronous stream.  Sharding changes no result: random numbers
+// and the accept history are keyed by the chain's index in its instance.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -36,9 +49,11 @@ struct Carver {
   }
 };
 
-struct Inst {
+// chains [chain0, chain0 + C) of instance `inst`
+struct Shard {
   // parameters
-  int L = 0, N = 0, Lam = 0, C = 0, mats = 0, k = 1, n_stab = 1, nb = 1, index = 0;
+  int L = 0, N = 0, Lam = 0, C = 0, mats = 0, k = 1, n_stab = 1, nb = 1;
+  int inst = 0, chain0 = 0, Ctot = 0;
   double U = 0, t = 0, beta = 0, dtau = 0, lambda = 0;
   uint64_t seed = 0;
   // device state (bulk = FP32 in mixed mode, FP64 otherwise)
@@ -54,27 +69,37 @@ struct Inst {
   double *Tq = nullptr;                  // compact-WY T factors of the blocked QR
   double *Sq = nullptr;                  // column-swap scratch of the blocked QR
   ChainStats *stats = nullptr;
-  int64_t *sweep_ctr = nullptr, *trace_base = nullptr;
-  uint8_t *trace = nullptr;
-  int64_t trace_alloc = 0;               // sweeps the trace buffer holds
-  int64_t trace_cap = 0;                 // sweeps of the current history window
+  int64_t *sweep_ctr = nullptr;
   MeasState ms{};
-  // host
+  // streams and host-side position
+  hipStream_t s = nullptr, aux = nullptr;
+  hipEvent_t ev_main = nullptr, ev_left = nullptr;
+  bool left_pending = false;             // a left rebuild on aux not yet waited for by s
   int slice = 1;
   int64_t sweeps = 0;
-  int64_t trace_host_base = 0;
 };
 
-size_t nn(const Inst &I) { return (size_t)I.N * I.N; }
+// one instance as the caller sees it: shards [first, first + count)
+struct UInst {
+  int first = 0, count = 0, C = 0, N = 0, Lam = 0;
+  uint8_t *trace = nullptr;              // [trace_alloc][C][Lam][N]
+  int64_t *trace_base = nullptr;         // sweep index of trace entry 0
+  int64_t trace_alloc = 0;               // sweeps the trace buffer holds
+  int64_t trace_cap = 0;                 // sweeps of the current history window
+};
+
+size_t nn(const Shard &I) { return (size_t)I.N * I.N; }
 
 }  // namespace
 
 struct bss_ctx {
-  std::vector<Inst> inst;
+  std::vector<Shard> sh;
+  std::vector<UInst> ui;
   bss_options opt{};
   bool fp64 = true;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipEvent_t ev_fork = nullptr;
   char *mem = nullptr;
   size_t mem_bytes = 0;
   bool own_mem = false;
@@ -123,9 +148,6 @@ struct Timed {
     c->fam[fam].pending.push_back({a, b});
   }
 };
-}  // namespace
-
-namespace {
 
 bss_status fail(bss_ctx *c, bss_status s, const std::string &msg) {
   if (c) c->last_error = msg;
@@ -167,7 +189,18 @@ int auto_nstab(double U, double dtau) {
   return std::max(1, std::min(n, 10));
 }
 
-void layout(Inst &I, bool fp64, Carver &cv, int64_t trace_sweeps, bool tracing) {
+// Shards per instance: two once each half still fills the GEMMs of a slice
+// (the environment variable BSS_SHARDS = 1..8 overrides, for tuning).
+int shard_count(int C) {
+  int s = C >= 32 ? 2 : 1;
+  if (const char *env = std::getenv("BSS_SHARDS")) {
+    const int v = std::atoi(env);
+    if (v >= 1 && v <= 8) s = v;
+  }
+  return std::max(1, std::min(s, C));
+}
+
+void layout_shard(Shard &I, bool fp64, Carver &cv) {
   const size_t NN = nn(I), M = (size_t)I.mats, bsz = fp64 ? 8 : 4;
   I.Em = cv.take<double>(NN);
   I.Ep = cv.take<double>(NN);
@@ -196,11 +229,8 @@ void layout(Inst &I, bool fp64, Carver &cv, int64_t trace_sweeps, bool tracing) 
   I.Sq = cv.take<double>(M * qr_scratch_doubles(I.N));
   I.stats = cv.take<ChainStats>(I.C);
   I.sweep_ctr = cv.take<int64_t>(1);
-  I.trace_base = cv.take<int64_t>(1);
-  I.trace_alloc = I.trace_cap = tracing ? trace_sweeps : 0;
-  I.trace = cv.take<uint8_t>(tracing ? (size_t)trace_sweeps * I.C * I.Lam * I.N : 1);
   I.ms.nbins = NBINS;
-  I.ms.nbins_g = I.C == 1 ? NBINS : 1;
+  I.ms.nbins_g = I.Ctot == 1 ? NBINS : 1;
   I.ms.glen = (long)(I.Lam + 1) * I.N;
   I.ms.docc = cv.take<double>((size_t)I.C * NBINS);
   I.ms.gk = cv.take<double>((size_t)I.C * I.ms.nbins_g * I.ms.glen);
@@ -209,21 +239,41 @@ void layout(Inst &I, bool fp64, Carver &cv, int64_t trace_sweeps, bool tracing) 
   I.ms.cur = cv.take<int>(I.C);
 }
 
-bool resolve(const bss_instance *in, int n, const bss_options &opt, std::vector<Inst> &out,
-             std::string &why, bss_status &code) {
+void layout_inst(UInst &U, Carver &cv, int64_t trace_sweeps, bool tracing) {
+  U.trace_alloc = U.trace_cap = tracing ? trace_sweeps : 0;
+  U.trace = cv.take<uint8_t>(tracing ? (size_t)trace_sweeps * U.C * U.Lam * U.N : 1);
+  U.trace_base = cv.take<int64_t>(1);
+}
+
+bool resolve(const bss_instance *in, int n, const bss_options &opt, std::vector<Shard> &out,
+             std::vector<UInst> &uis, std::string &why, bss_status &code) {
   out.clear();
+  uis.clear();
   for (int i = 0; i < n; ++i) {
     if (!valid_instance(in[i], why, code)) { why = "instance " + std::to_string(i) + ": " + why; return false; }
-    Inst I;
+    Shard I;
     I.L = in[i].L; I.N = I.L * I.L; I.U = in[i].U; I.t = in[i].t; I.beta = in[i].beta; I.dtau = in[i].dtau;
     I.Lam = (int)std::lround(I.beta / I.dtau);
-    I.C = in[i].n_chains; I.mats = 2 * I.C; I.seed = in[i].seed; I.index = i;
+    I.Ctot = in[i].n_chains; I.seed = in[i].seed; I.inst = i;
     I.lambda = std::acosh(std::exp(0.5 * I.dtau * I.U));
     I.k = opt.delay_k > 0 ? opt.delay_k : auto_k(I.N);
     I.n_stab = opt.n_stab > 0 ? opt.n_stab : auto_nstab(I.U, I.dtau);
     I.n_stab = std::min(I.n_stab, I.Lam);
     I.nb = (I.Lam + I.n_stab - 1) / I.n_stab;
-    out.push_back(I);
+    UInst U;
+    U.first = (int)out.size();
+    U.C = I.Ctot; U.N = I.N; U.Lam = I.Lam;
+    U.count = shard_count(I.Ctot);
+    int c0 = 0;
+    for (int s = 0; s < U.count; ++s) {
+      Shard J = I;
+      J.C = I.Ctot / U.count + (s < I.Ctot % U.count ? 1 : 0);
+      J.chain0 = c0;
+      J.mats = 2 * J.C;
+      c0 += J.C;
+      out.push_back(J);
+    }
+    uis.push_back(U);
   }
   return true;
 }
@@ -241,15 +291,23 @@ bool check_options(const bss_options *o, std::string &why) {
   return true;
 }
 
-size_t total_bytes(std::vector<Inst> &v, const bss_options &opt) {
-  Carver cv;
+// lays the whole context out on `cv` (error word first)
+void layout_all(std::vector<Shard> &v, std::vector<UInst> &u, const bss_options &opt, Carver &cv, int **err) {
+  int *e = cv.take<int>(4);
+  if (err) *err = e;
   const bool tracing = (opt.flags & (BSS_FLAG_RECORD_TRACE | BSS_FLAG_REPLAY_TRACE)) != 0;
-  for (auto &I : v) layout(I, opt.precision == BSS_PREC_FP64, cv, std::max(opt.trace_sweeps, 1), tracing);
+  for (auto &I : v) layout_shard(I, opt.precision == BSS_PREC_FP64, cv);
+  for (auto &U : u) layout_inst(U, cv, std::max(opt.trace_sweeps, 1), tracing);
+}
+
+size_t total_bytes(std::vector<Shard> &v, std::vector<UInst> &u, const bss_options &opt) {
+  Carver cv;
+  layout_all(v, u, opt, cv, nullptr);
   return cv.off + 256;
 }
 
 // ---------------------------------------------------------------------------
-// launch schedule
+// launch schedule of one shard
 
 GemmDesc gemm_desc(int N, int batch) {
   GemmDesc d{};
@@ -263,9 +321,11 @@ GemmDesc gemm_desc(int N, int batch) {
 
 struct Exec {
   bss_ctx *c;
-  Inst &I;
-  hipStream_t s;
+  Shard &I;
+  const UInst &U;
+  hipStream_t s;   // stream the current phase is issued on
   hipError_t e = hipSuccess;
+  Exec(bss_ctx *c_, Shard &I_) : c(c_), I(I_), U(c_->ui[I_.inst]), s(I_.s) {}
   void chk(hipError_t x) { if (e == hipSuccess && x != hipSuccess) e = x; }
 
   size_t NN() const { return nn(I); }
@@ -276,6 +336,14 @@ struct Exec {
   double *LU(int b) const { return I.LU + (size_t)b * I.mats * NN(); }
   double *LD(int b) const { return I.LD + (size_t)b * I.mats * I.N; }
   double *LV(int b) const { return I.LV + (size_t)b * I.mats * NN(); }
+
+  // the main stream waits for an outstanding left rebuild before it touches
+  // the left factors, the block products or the QR scratch
+  void wait_left() {
+    if (!I.left_pending) return;
+    chk(hipStreamWaitEvent(I.s, I.ev_left, 0));
+    I.left_pending = false;
+  }
 
   void gemm64(const double *A, bool ta, const double *B, bool tb, double *C, long sA, long sB,
               const double *ks = nullptr, long sks = 0, const double *cs = nullptr, long scs = 0) {
@@ -315,7 +383,7 @@ struct Exec {
   }
 
   // G = (I + R L)^{-1} from the right chain after block b and left entry b
-  // (none for the last block), into Gf.  With rhs_v the right-hand side is
+  // (none for the last block), into out.  With rhs_v the right-hand side is
   // Ds_R V_R instead, which yields G(tau_{l_b}, 0) (time-displaced).
   void fresh(int b, bool rhs_v, double *out) {
     const bool left = b < I.nb - 1;
@@ -355,7 +423,8 @@ struct Exec {
 
   // full recomputation from the current field (creation, set_field, load)
   void initialise(bool draw_field) {
-    if (draw_field) chk(init_field(I.h, I.C, I.Lam, I.N, I.seed, (uint64_t)I.index, s));
+    wait_left();
+    if (draw_field) chk(init_field(I.h, I.C, I.Lam, I.N, I.seed + (uint64_t)I.chain0, (uint64_t)I.inst, s));
     for (int b = 0; b < I.nb; ++b) {
       block_product(b);
       right_update(b);
@@ -368,16 +437,17 @@ struct Exec {
   void flip(int l) {
     FlipArgs a{};
     a.N = I.N; a.Lam = I.Lam; a.l = l; a.k = I.k; a.chains = I.C;
+    a.chain0 = I.chain0; a.chains_total = I.Ctot;
     a.G = I.G; a.h = I.h; a.dv = I.dv;
     a.dlt_up_p = std::exp(-2.0 * I.lambda) - 1.0;   // sigma = +1, h = +1
     a.dlt_up_m = std::exp(2.0 * I.lambda) - 1.0;    // sigma = +1, h = -1
     a.dlt_dn_p = std::exp(2.0 * I.lambda) - 1.0;    // sigma = -1, h = +1
     a.dlt_dn_m = std::exp(-2.0 * I.lambda) - 1.0;   // sigma = -1, h = -1
     a.elam = std::exp(I.lambda); a.emlam = std::exp(-I.lambda);
-    a.seed = I.seed; a.inst = (uint64_t)I.index;
+    a.seed = I.seed; a.inst = (uint64_t)I.inst;
     a.sweep = I.sweep_ctr;
     a.trace_mode = (c->opt.flags & BSS_FLAG_RECORD_TRACE) ? 1 : ((c->opt.flags & BSS_FLAG_REPLAY_TRACE) ? 2 : 0);
-    a.trace = I.trace; a.trace_base = I.trace_base; a.trace_sweeps = I.trace_cap;
+    a.trace = U.trace; a.trace_base = U.trace_base; a.trace_sweeps = U.trace_cap;
     a.stats = I.stats; a.err = c->err;
     Timed tm(c, F_FLIP, s);
     chk(flip_slice(a, c->fp64, s));
@@ -403,6 +473,7 @@ struct Exec {
   }
 
   void stabilise(int l) {
+    wait_left();
     const int b = (l - 1) / I.n_stab;
     block_product(b);
     right_update(b);
@@ -417,14 +488,22 @@ struct Exec {
     if (l % I.n_stab == 0 || l == I.Lam) stabilise(l);
   }
 
+  // sweep counter on the main stream, left rebuild on the aux stream
   void end_of_sweep() {
+    chk(bump_counter(I.sweep_ctr, I.s));
+    chk(hipEventRecord(I.ev_main, I.s));
+    chk(hipStreamWaitEvent(I.aux, I.ev_main, 0));
+    s = I.aux;
     left_rebuild();
-    chk(bump_counter(I.sweep_ctr, s));
+    s = I.s;
+    chk(hipEventRecord(I.ev_left, I.aux));
+    I.left_pending = true;
   }
 
   // measurement of the sweep just finished: Gf holds G(0) = G(1) fresh, the
   // right chain after each block and the rebuilt left factors are current.
   void measure() {
+    wait_left();
     chk(meas_begin(I.ms, I.C, s));
     chk(meas_docc(I.ms, I.Gf, I.C, I.N, s));
     chk(hipMemcpyAsync(I.Gt, I.Gf, sizeof(double) * I.mats * NN(), hipMemcpyDeviceToDevice, s));
@@ -443,6 +522,25 @@ struct Exec {
     chk(meas_end(I.ms, I.C, s));
   }
 };
+
+// every shard's main stream starts after the work already on the context stream
+hipError_t fork(bss_ctx *c) {
+  hipError_t e = hipEventRecord(c->ev_fork, c->stream);
+  for (auto &I : c->sh)
+    if (e == hipSuccess) e = hipStreamWaitEvent(I.s, c->ev_fork, 0);
+  return e;
+}
+
+// the context stream waits for all work of every shard (main and aux)
+hipError_t join(bss_ctx *c) {
+  hipError_t e = hipSuccess;
+  for (auto &I : c->sh) {
+    if (e == hipSuccess) e = hipEventRecord(I.ev_main, I.s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, I.ev_main, 0);
+    if (e == hipSuccess && I.left_pending) e = hipStreamWaitEvent(c->stream, I.ev_left, 0);
+  }
+  return e;
+}
 
 bss_status check_err(bss_ctx *c) {
   if (c->poisoned) return fail(c, BSS_E_STATE, "context poisoned by an earlier numerical failure");
@@ -469,6 +567,11 @@ bss_status usable(bss_ctx *c) {
   return BSS_OK;
 }
 
+bss_status exec_failed(bss_ctx *c, const Exec &x) {
+  c->poisoned = true;
+  return fail(c, BSS_E_DEVICE, hipGetErrorString(x.e));
+}
+
 bss_status create_impl(const bss_instance *in, int n, const bss_options *opt_in, bss_ctx **out) {
   if (!out) return BSS_E_INVALID_ARG;
   *out = nullptr;
@@ -478,14 +581,16 @@ bss_status create_impl(const bss_instance *in, int n, const bss_options *opt_in,
   bss_options opt;
   bss_options_default(&opt);
   if (opt_in) opt = *opt_in;
-  std::vector<Inst> v;
+  std::vector<Shard> v;
+  std::vector<UInst> u;
   bss_status code;
-  if (!resolve(in, n, opt, v, why, code)) return code;
+  if (!resolve(in, n, opt, v, u, why, code)) return code;
   bss_ctx *c = new (std::nothrow) bss_ctx;
   if (!c) return BSS_E_OUT_OF_MEMORY;
   c->opt = opt;
   c->fp64 = opt.precision == BSS_PREC_FP64;
-  c->inst = v;
+  c->sh = v;
+  c->ui = u;
   c->fam.resize(F_COUNT);
   for (int f = 0; f < F_COUNT; ++f) c->fam[f].name = FAM_NAMES[f];
   auto bail = [&](bss_status s) { bss_destroy(c); return s; };
@@ -495,7 +600,14 @@ bss_status create_impl(const bss_instance *in, int n, const bss_options *opt_in,
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return bail(BSS_E_DEVICE);
     c->own_stream = true;
   }
-  const size_t need = total_bytes(c->inst, opt) + 4096;
+  if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess) return bail(BSS_E_DEVICE);
+  for (auto &I : c->sh) {
+    if (hipStreamCreateWithFlags(&I.s, hipStreamNonBlocking) != hipSuccess) return bail(BSS_E_DEVICE);
+    if (hipStreamCreateWithFlags(&I.aux, hipStreamNonBlocking) != hipSuccess) return bail(BSS_E_DEVICE);
+    if (hipEventCreateWithFlags(&I.ev_main, hipEventDisableTiming) != hipSuccess) return bail(BSS_E_DEVICE);
+    if (hipEventCreateWithFlags(&I.ev_left, hipEventDisableTiming) != hipSuccess) return bail(BSS_E_DEVICE);
+  }
+  const size_t need = total_bytes(c->sh, c->ui, opt) + 4096;
   if (opt.workspace) {
     if (opt.workspace_bytes < need) return bail(BSS_E_OUT_OF_MEMORY);
     c->mem = (char *)opt.workspace;
@@ -507,26 +619,25 @@ bss_status create_impl(const bss_instance *in, int n, const bss_options *opt_in,
   }
   Carver cv;
   cv.base = c->mem;
-  c->err = cv.take<int>(4);
-  c->profile = (opt.flags & BSS_FLAG_PROFILE) != 0;   // creation work is not profiled
-
-  const bool tracing = (opt.flags & (BSS_FLAG_RECORD_TRACE | BSS_FLAG_REPLAY_TRACE)) != 0;
-  for (auto &I : c->inst) layout(I, c->fp64, cv, std::max(opt.trace_sweeps, 1), tracing);
+  layout_all(c->sh, c->ui, opt, cv, &c->err);
+  c->profile = (opt.flags & BSS_FLAG_PROFILE) != 0;   // creation work is dropped from the profile below
   hipStream_t s = c->stream;
   if (hipMemsetAsync(c->mem, 0, cv.off, s) != hipSuccess) return bail(BSS_E_DEVICE);
   if (hipStreamSynchronize(s) != hipSuccess) return bail(BSS_E_DEVICE);
-  for (auto &I : c->inst) {
+  for (auto &I : c->sh) {
     std::vector<int64_t> ones(I.C, 1);
     if (hipMemcpy(I.ms.binsize, ones.data(), sizeof(int64_t) * I.C, hipMemcpyHostToDevice) != hipSuccess)
       return bail(BSS_E_DEVICE);
   }
-  for (auto &I : c->inst) {
-    Exec x{c, I, s};
-    x.chk(build_exp(I.L, I.t, I.dtau, I.Em, I.Ep, c->fp64 ? nullptr : I.Etm, c->fp64 ? nullptr : I.Etp, c->fp64, s));
+  if (fork(c) != hipSuccess) return bail(BSS_E_DEVICE);
+  for (auto &I : c->sh) {
+    Exec x(c, I);
+    x.chk(build_exp(I.L, I.t, I.dtau, I.Em, I.Ep, c->fp64 ? nullptr : I.Etm, c->fp64 ? nullptr : I.Etp, c->fp64,
+                    I.s));
     x.initialise(true);
     if (x.e != hipSuccess) { c->last_error = hipGetErrorString(x.e); return bail(BSS_E_DEVICE); }
   }
-  if (hipStreamSynchronize(s) != hipSuccess) return bail(BSS_E_DEVICE);
+  if (join(c) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return bail(BSS_E_DEVICE);
   for (auto &f : c->fam) {
     for (auto &p : f.pending) { c->pool.push_back(p.first); c->pool.push_back(p.second); }
     f.pending.clear();
@@ -566,10 +677,11 @@ bss_status bss_workspace_size(const bss_instance *inst, int32_t n_inst, const bs
   bss_options opt;
   bss_options_default(&opt);
   if (opt_in) opt = *opt_in;
-  std::vector<Inst> v;
+  std::vector<Shard> v;
+  std::vector<UInst> u;
   bss_status code;
-  if (!resolve(inst, n_inst, opt, v, why, code)) return code;
-  *bytes = total_bytes(v, opt) + 4096 + 256;
+  if (!resolve(inst, n_inst, opt, v, u, why, code)) return code;
+  *bytes = total_bytes(v, u, opt) + 4096 + 256;
   return BSS_OK;
 }
 
@@ -577,18 +689,31 @@ bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure) {
   bss_status st = usable(c);
   if (st != BSS_OK) return st;
   if (n_sweeps < 0) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be >= 0");
-  for (auto &I : c->inst)
+  for (auto &I : c->sh)
     if (I.slice != 1) return fail(c, BSS_E_STATE, "an instance is part-way through a sweep");
+  if (n_sweeps == 0) return BSS_OK;
+  HIP_TRY(c, fork(c));
+  int lam_max = 0;
+  for (auto &I : c->sh) lam_max = std::max(lam_max, I.Lam);
+  std::vector<Exec> xs;
+  xs.reserve(c->sh.size());
+  for (auto &I : c->sh) xs.emplace_back(c, I);
   for (int sw = 0; sw < n_sweeps; ++sw) {
-    for (auto &I : c->inst) {
-      Exec x{c, I, c->stream};
-      for (int l = 1; l <= I.Lam; ++l) x.slice(l);
-      x.end_of_sweep();
-      if (measure) x.measure();
-      if (x.e != hipSuccess) { c->poisoned = true; return fail(c, BSS_E_DEVICE, hipGetErrorString(x.e)); }
-      I.sweeps += 1;
+    // slice by slice across the shards, so that their streams overlap
+    for (int l = 1; l <= lam_max; ++l)
+      for (auto &x : xs) {
+        if (l > x.I.Lam) continue;
+        x.slice(l);
+        if (l == x.I.Lam) x.end_of_sweep();
+      }
+    if (measure)
+      for (auto &x : xs) x.measure();
+    for (auto &x : xs) {
+      if (x.e != hipSuccess) return exec_failed(c, x);
+      x.I.sweeps += 1;
     }
   }
+  HIP_TRY(c, join(c));
   return BSS_OK;
 }
 
@@ -596,9 +721,14 @@ bss_status bss_step_slices(bss_ctx *c, int32_t n_slices) {
   bss_status st = usable(c);
   if (st != BSS_OK) return st;
   if (n_slices < 0) return fail(c, BSS_E_INVALID_ARG, "n_slices must be >= 0");
-  for (auto &I : c->inst) {
-    Exec x{c, I, c->stream};
-    for (int n = 0; n < n_slices; ++n) {
+  if (n_slices == 0) return BSS_OK;
+  HIP_TRY(c, fork(c));
+  std::vector<Exec> xs;
+  xs.reserve(c->sh.size());
+  for (auto &I : c->sh) xs.emplace_back(c, I);
+  for (int n = 0; n < n_slices; ++n)
+    for (auto &x : xs) {
+      Shard &I = x.I;
       x.slice(I.slice);
       if (I.slice == I.Lam) {
         x.end_of_sweep();
@@ -607,139 +737,178 @@ bss_status bss_step_slices(bss_ctx *c, int32_t n_slices) {
       } else {
         I.slice += 1;
       }
+      if (x.e != hipSuccess) return exec_failed(c, x);
     }
-    if (x.e != hipSuccess) { c->poisoned = true; return fail(c, BSS_E_DEVICE, hipGetErrorString(x.e)); }
-  }
+  HIP_TRY(c, join(c));
   return BSS_OK;
 }
 
-static bss_status pick(bss_ctx *c, int32_t inst, Inst **I) {
+}  // extern "C"
+
+namespace {
+
+bss_status pick(bss_ctx *c, int32_t inst, UInst **U) {
   bss_status st = usable(c);
   if (st != BSS_OK) return st;
-  if (inst < 0 || inst >= (int)c->inst.size()) return fail(c, BSS_E_INVALID_ARG, "instance index out of range");
-  *I = &c->inst[inst];
+  if (inst < 0 || inst >= (int)c->ui.size()) return fail(c, BSS_E_INVALID_ARG, "instance index out of range");
+  *U = &c->ui[inst];
   return BSS_OK;
 }
 
+// the shard of an instance that holds chain `chain`
+Shard &shard_of(bss_ctx *c, const UInst &U, int chain) {
+  for (int k = 0; k + 1 < U.count; ++k) {
+    Shard &I = c->sh[U.first + k];
+    if (chain < I.chain0 + I.C) return I;
+  }
+  return c->sh[U.first + U.count - 1];
+}
+
+}  // namespace
+
+extern "C" {
+
 bss_status bss_get_green(bss_ctx *c, int32_t inst, int32_t chain, int32_t spin, double *out) {
-  Inst *I;
-  bss_status st = pick(c, inst, &I);
+  UInst *U;
+  bss_status st = pick(c, inst, &U);
   if (st != BSS_OK) return st;
-  if (chain < 0 || chain >= I->C || (spin != 0 && spin != 1) || !out) return fail(c, BSS_E_INVALID_ARG, "bad chain/spin/out");
+  if (chain < 0 || chain >= U->C || (spin != 0 && spin != 1) || !out) return fail(c, BSS_E_INVALID_ARG, "bad chain/spin/out");
   if ((st = check_err(c)) != BSS_OK) return st;
-  const size_t n = nn(*I);
-  const size_t off = (size_t)(2 * chain + spin) * n;
+  Shard &I = shard_of(c, *U, chain);
+  const size_t n = nn(I);
+  const size_t off = (size_t)(2 * (chain - I.chain0) + spin) * n;
   if (c->fp64) {
-    HIP_TRY(c, hipMemcpy(out, (double *)I->G + off, sizeof(double) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(out, (double *)I.G + off, sizeof(double) * n, hipMemcpyDeviceToHost));
   } else {
     std::vector<float> tmp(n);
-    HIP_TRY(c, hipMemcpy(tmp.data(), (float *)I->G + off, sizeof(float) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(tmp.data(), (float *)I.G + off, sizeof(float) * n, hipMemcpyDeviceToHost));
     for (size_t e = 0; e < n; ++e) out[e] = tmp[e];
   }
   return BSS_OK;
 }
 
 bss_status bss_get_field(bss_ctx *c, int32_t inst, int32_t chain, int8_t *out) {
-  Inst *I;
-  bss_status st = pick(c, inst, &I);
+  UInst *U;
+  bss_status st = pick(c, inst, &U);
   if (st != BSS_OK) return st;
-  if (chain < 0 || chain >= I->C || !out) return fail(c, BSS_E_INVALID_ARG, "bad chain/out");
+  if (chain < 0 || chain >= U->C || !out) return fail(c, BSS_E_INVALID_ARG, "bad chain/out");
   if ((st = check_err(c)) != BSS_OK) return st;
-  const size_t n = (size_t)I->Lam * I->N;
-  HIP_TRY(c, hipMemcpy(out, I->h + (size_t)chain * n, n, hipMemcpyDeviceToHost));
+  Shard &I = shard_of(c, *U, chain);
+  const size_t n = (size_t)I.Lam * I.N;
+  HIP_TRY(c, hipMemcpy(out, I.h + (size_t)(chain - I.chain0) * n, n, hipMemcpyDeviceToHost));
   return BSS_OK;
 }
 
 bss_status bss_set_field(bss_ctx *c, int32_t inst, int32_t chain, const int8_t *in) {
-  Inst *I;
-  bss_status st = pick(c, inst, &I);
+  UInst *U;
+  bss_status st = pick(c, inst, &U);
   if (st != BSS_OK) return st;
-  if (chain < 0 || chain >= I->C || !in) return fail(c, BSS_E_INVALID_ARG, "bad chain/in");
-  for (auto &J : c->inst)
+  if (chain < 0 || chain >= U->C || !in) return fail(c, BSS_E_INVALID_ARG, "bad chain/in");
+  for (auto &J : c->sh)
     if (J.slice != 1) return fail(c, BSS_E_STATE, "set_field needs every instance at slice 1");
-  const size_t n = (size_t)I->Lam * I->N;
+  Shard &I = shard_of(c, *U, chain);
+  const size_t n = (size_t)I.Lam * I.N;
   for (size_t e = 0; e < n; ++e)
     if (in[e] != 1 && in[e] != -1) return fail(c, BSS_E_INVALID_ARG, "field entries must be +-1");
   if ((st = check_err(c)) != BSS_OK) return st;
-  HIP_TRY(c, hipMemcpy(I->h + (size_t)chain * n, in, n, hipMemcpyHostToDevice));
-  Exec x{c, *I, c->stream};
+  HIP_TRY(c, hipMemcpy(I.h + (size_t)(chain - I.chain0) * n, in, n, hipMemcpyHostToDevice));
+  HIP_TRY(c, fork(c));
+  Exec x(c, I);
   x.initialise(false);
-  if (x.e != hipSuccess) { c->poisoned = true; return fail(c, BSS_E_DEVICE, hipGetErrorString(x.e)); }
+  if (x.e != hipSuccess) return exec_failed(c, x);
+  HIP_TRY(c, join(c));
   return check_err(c);
 }
 
 bss_status bss_set_trace(bss_ctx *c, int32_t inst, const uint8_t *accept, int32_t n_sweeps) {
-  Inst *I;
-  bss_status st = pick(c, inst, &I);
+  UInst *U;
+  bss_status st = pick(c, inst, &U);
   if (st != BSS_OK) return st;
   if (!(c->opt.flags & BSS_FLAG_REPLAY_TRACE)) return fail(c, BSS_E_STATE, "context not created with BSS_FLAG_REPLAY_TRACE");
-  if (!accept || n_sweeps < 1 || n_sweeps > I->trace_alloc) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be in 1..trace_sweeps");
-  if (I->slice != 1) return fail(c, BSS_E_STATE, "set_trace needs the instance at slice 1");
+  if (!accept || n_sweeps < 1 || n_sweeps > U->trace_alloc) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be in 1..trace_sweeps");
+  for (int k = 0; k < U->count; ++k)
+    if (c->sh[U->first + k].slice != 1) return fail(c, BSS_E_STATE, "set_trace needs the instance at slice 1");
   if ((st = check_err(c)) != BSS_OK) return st;
-  const size_t n = (size_t)n_sweeps * I->C * I->Lam * I->N;
-  HIP_TRY(c, hipMemcpy(I->trace, accept, n, hipMemcpyHostToDevice));
-  int64_t base = I->sweeps;
-  HIP_TRY(c, hipMemcpy(I->trace_base, &base, sizeof(base), hipMemcpyHostToDevice));
-  I->trace_cap = n_sweeps;   // sweeping past this window is an error
+  const size_t n = (size_t)n_sweeps * U->C * U->Lam * U->N;
+  HIP_TRY(c, hipMemcpy(U->trace, accept, n, hipMemcpyHostToDevice));
+  int64_t base = c->sh[U->first].sweeps;
+  HIP_TRY(c, hipMemcpy(U->trace_base, &base, sizeof(base), hipMemcpyHostToDevice));
+  U->trace_cap = n_sweeps;   // sweeping past this window is an error
   return BSS_OK;
 }
 
 bss_status bss_get_trace(bss_ctx *c, int32_t inst, uint8_t *accept, int32_t n_sweeps) {
-  Inst *I;
-  bss_status st = pick(c, inst, &I);
+  UInst *U;
+  bss_status st = pick(c, inst, &U);
   if (st != BSS_OK) return st;
   if (!(c->opt.flags & BSS_FLAG_RECORD_TRACE)) return fail(c, BSS_E_STATE, "context not created with BSS_FLAG_RECORD_TRACE");
-  if (!accept || n_sweeps < 1 || n_sweeps > I->trace_cap) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be in 1..trace_sweeps");
+  if (!accept || n_sweeps < 1 || n_sweeps > U->trace_cap) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be in 1..trace_sweeps");
   if ((st = check_err(c)) != BSS_OK) return st;
-  const size_t n = (size_t)n_sweeps * I->C * I->Lam * I->N;
-  HIP_TRY(c, hipMemcpy(accept, I->trace, n, hipMemcpyDeviceToHost));
+  const size_t n = (size_t)n_sweeps * U->C * U->Lam * U->N;
+  HIP_TRY(c, hipMemcpy(accept, U->trace, n, hipMemcpyDeviceToHost));
   return BSS_OK;
 }
 
 bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
-  Inst *I;
-  bss_status st = pick(c, inst, &I);
+  UInst *U;
+  bss_status st = pick(c, inst, &U);
   if (st != BSS_OK) return st;
   if (!out) return fail(c, BSS_E_INVALID_ARG, "out is NULL");
   if ((st = check_err(c)) != BSS_OK) return st;
-  std::vector<ChainStats> cs(I->C);
-  HIP_TRY(c, hipMemcpy(cs.data(), I->stats, sizeof(ChainStats) * I->C, hipMemcpyDeviceToHost));
   std::memset(out, 0, sizeof(*out));
-  out->sweeps = I->sweeps;
   out->sign = 1;
   double dsum = 0;
   int64_t dcnt = 0;
-  for (auto &x : cs) {
-    out->proposals += x.proposals;
-    out->accepted += x.accepted;
-    out->logw += x.logw;
-    out->drift_max = std::max(out->drift_max, x.drift_max);
-    dsum += x.drift_sum;
-    dcnt += x.drift_count;
+  for (int k = 0; k < U->count; ++k) {
+    const Shard &I = c->sh[U->first + k];
+    std::vector<ChainStats> cs(I.C);
+    HIP_TRY(c, hipMemcpy(cs.data(), I.stats, sizeof(ChainStats) * I.C, hipMemcpyDeviceToHost));
+    for (auto &x : cs) {
+      out->proposals += x.proposals;
+      out->accepted += x.accepted;
+      out->logw += x.logw;
+      out->drift_max = std::max(out->drift_max, x.drift_max);
+      dsum += x.drift_sum;
+      dcnt += x.drift_count;
+    }
+    out->sweeps = I.sweeps;
+    out->N = I.N; out->Lambda = I.Lam; out->delay_k = I.k; out->n_stab = I.n_stab;
   }
   out->drift_mean = dcnt ? dsum / dcnt : 0.0;
-  out->n_chains = I->C;
-  out->N = I->N; out->Lambda = I->Lam; out->delay_k = I->k; out->n_stab = I->n_stab;
+  out->n_chains = U->C;
   return BSS_OK;
 }
 
-static bss_status fetch_meas(bss_ctx *c, Inst *I, std::vector<double> &docc, std::vector<double> &gk,
-                             std::vector<int64_t> &count, std::vector<int64_t> &binsize) {
-  docc.resize((size_t)I->C * NBINS);
-  gk.resize((size_t)I->C * I->ms.nbins_g * I->ms.glen);
-  count.resize(I->C);
-  binsize.resize(I->C);
-  HIP_TRY(c, hipMemcpy(docc.data(), I->ms.docc, sizeof(double) * docc.size(), hipMemcpyDeviceToHost));
-  HIP_TRY(c, hipMemcpy(gk.data(), I->ms.gk, sizeof(double) * gk.size(), hipMemcpyDeviceToHost));
-  HIP_TRY(c, hipMemcpy(count.data(), I->ms.count, sizeof(int64_t) * I->C, hipMemcpyDeviceToHost));
-  HIP_TRY(c, hipMemcpy(binsize.data(), I->ms.binsize, sizeof(int64_t) * I->C, hipMemcpyDeviceToHost));
+}  // extern "C"
+
+namespace {
+
+// per-chain measurement arrays of one instance, in chain order
+bss_status fetch_meas(bss_ctx *c, const UInst &U, std::vector<double> &docc, std::vector<double> &gk,
+                      std::vector<int64_t> &count, std::vector<int64_t> &binsize, size_t &glen) {
+  const Shard &F = c->sh[U.first];
+  glen = (size_t)F.ms.glen;
+  const size_t gper = (size_t)F.ms.nbins_g * glen;
+  docc.resize((size_t)U.C * NBINS);
+  gk.resize((size_t)U.C * gper);
+  count.resize(U.C);
+  binsize.resize(U.C);
+  for (int k = 0; k < U.count; ++k) {
+    const Shard &I = c->sh[U.first + k];
+    const size_t c0 = I.chain0;
+    HIP_TRY(c, hipMemcpy(docc.data() + c0 * NBINS, I.ms.docc, sizeof(double) * I.C * NBINS, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(gk.data() + c0 * gper, I.ms.gk, sizeof(double) * I.C * gper, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(count.data() + c0, I.ms.count, sizeof(int64_t) * I.C, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(binsize.data() + c0, I.ms.binsize, sizeof(int64_t) * I.C, hipMemcpyDeviceToHost));
+  }
   return BSS_OK;
 }
 
-// mean and standard error of per-chain sums (>= 2 chains) or of the complete
-// bins of one chain; vals[c or bin][e]
-static void mean_err(const std::vector<std::vector<double>> &samples, const std::vector<double> &weights,
-                     size_t len, double *mean, double *err) {
+// mean and standard error of per-sample sums: samples[s] sums weights[s]
+// measurements; the mean is over all measurements, the error is that of the
+// mean of the per-sample means
+void mean_err(const std::vector<std::vector<double>> &samples, const std::vector<double> &weights, size_t len,
+              double *mean, double *err) {
   const size_t S = samples.size();
   double wsum = 0;
   for (double w : weights) wsum += w;
@@ -749,10 +918,8 @@ static void mean_err(const std::vector<std::vector<double>> &samples, const std:
     m /= wsum;
     if (mean) mean[e] = m;
     if (err) {
-      // samples[s][e] are sums over weights[s] measurements; use their means
-      double acc = 0;
+      double acc = 0, mm = 0;
       size_t n = 0;
-      double mm = 0;
       for (size_t s = 0; s < S; ++s) if (weights[s] > 0) { mm += samples[s][e] / weights[s]; ++n; }
       mm = n ? mm / n : 0;
       for (size_t s = 0; s < S; ++s) if (weights[s] > 0) { const double d = samples[s][e] / weights[s] - mm; acc += d * d; }
@@ -761,22 +928,22 @@ static void mean_err(const std::vector<std::vector<double>> &samples, const std:
   }
 }
 
-static bss_status measure_common(bss_ctx *c, int32_t inst, bool gk_wanted, double *mean, double *err, int64_t len) {
-  Inst *I;
-  bss_status st = pick(c, inst, &I);
+bss_status measure_common(bss_ctx *c, int32_t inst, bool gk_wanted, double *mean, double *err, int64_t len) {
+  UInst *U;
+  bss_status st = pick(c, inst, &U);
   if (st != BSS_OK) return st;
   if (!mean) return fail(c, BSS_E_INVALID_ARG, "mean is NULL");
-  if (gk_wanted && len != I->ms.glen) return fail(c, BSS_E_INVALID_ARG, "len must be (Lambda+1)*N");
+  if (gk_wanted && len != (int64_t)(U->Lam + 1) * U->N) return fail(c, BSS_E_INVALID_ARG, "len must be (Lambda+1)*N");
   if ((st = check_err(c)) != BSS_OK) return st;
   std::vector<double> docc, gk;
   std::vector<int64_t> count, binsize;
-  if ((st = fetch_meas(c, I, docc, gk, count, binsize)) != BSS_OK) return st;
+  size_t glen = 0;
+  if ((st = fetch_meas(c, *U, docc, gk, count, binsize, glen)) != BSS_OK) return st;
   if (count[0] == 0) return fail(c, BSS_E_STATE, "no measurements accumulated");
-  const size_t glen = (size_t)I->ms.glen;
   std::vector<std::vector<double>> samples;
   std::vector<double> weights;
-  if (I->C >= 2) {
-    for (int ch = 0; ch < I->C; ++ch) {
+  if (U->C >= 2) {
+    for (int ch = 0; ch < U->C; ++ch) {
       if (gk_wanted) samples.emplace_back(gk.begin() + (size_t)ch * glen, gk.begin() + (size_t)(ch + 1) * glen);
       else {
         double s = 0;
@@ -810,6 +977,48 @@ static bss_status measure_common(bss_ctx *c, int32_t inst, bool gk_wanted, doubl
   return BSS_OK;
 }
 
+// Checkpoint layout: magic, number of instances, then per instance C, Lam,
+// N, sweeps (int64 each) followed by, for all chains in order, the fields,
+// the chain statistics, the double-occupancy bins, the G(tau,k) bins, the
+// measurement counts and the bin sizes.  The layout does not depend on how
+// the chains are sharded.
+const uint64_t CK_MAGIC = 0x31504B4353534221ull;
+
+size_t inst_ck_bytes(const bss_ctx *c, const UInst &U) {
+  const Shard &F = c->sh[U.first];
+  return 32 + (size_t)U.C * U.Lam * U.N + sizeof(ChainStats) * U.C + sizeof(double) * U.C * NBINS +
+         sizeof(double) * U.C * F.ms.nbins_g * F.ms.glen + 2 * sizeof(int64_t) * U.C;
+}
+
+// one per-chain section of the checkpoint: `per(I)` bytes per chain at `dev(I)`
+template <typename Dev>
+bss_status ck_section(bss_ctx *c, const UInst &U, char *&p, size_t per, Dev dev, bool save) {
+  for (int k = 0; k < U.count; ++k) {
+    Shard &I = c->sh[U.first + k];
+    const size_t n = per * I.C;
+    if (save) HIP_TRY(c, hipMemcpy(p, dev(I), n, hipMemcpyDeviceToHost));
+    else HIP_TRY(c, hipMemcpy(dev(I), p, n, hipMemcpyHostToDevice));
+    p += n;
+  }
+  return BSS_OK;
+}
+
+bss_status ck_transfer(bss_ctx *c, const UInst &U, char *&p, bool save) {
+  const Shard &F = c->sh[U.first];
+  const size_t gper = sizeof(double) * F.ms.nbins_g * F.ms.glen;
+  bss_status st;
+  if ((st = ck_section(c, U, p, (size_t)U.Lam * U.N, [](Shard &I) { return (void *)I.h; }, save)) != BSS_OK) return st;
+  if ((st = ck_section(c, U, p, sizeof(ChainStats), [](Shard &I) { return (void *)I.stats; }, save)) != BSS_OK) return st;
+  if ((st = ck_section(c, U, p, sizeof(double) * NBINS, [](Shard &I) { return (void *)I.ms.docc; }, save)) != BSS_OK) return st;
+  if ((st = ck_section(c, U, p, gper, [](Shard &I) { return (void *)I.ms.gk; }, save)) != BSS_OK) return st;
+  if ((st = ck_section(c, U, p, sizeof(int64_t), [](Shard &I) { return (void *)I.ms.count; }, save)) != BSS_OK) return st;
+  return ck_section(c, U, p, sizeof(int64_t), [](Shard &I) { return (void *)I.ms.binsize; }, save);
+}
+
+}  // namespace
+
+extern "C" {
+
 bss_status bss_measure_gtau_k(bss_ctx *c, int32_t inst, double *mean, double *err, int64_t len) {
   return measure_common(c, inst, true, mean, err, len);
 }
@@ -822,47 +1031,35 @@ bss_status bss_reset_measurements(bss_ctx *c) {
   bss_status st = usable(c);
   if (st != BSS_OK) return st;
   if ((st = check_err(c)) != BSS_OK) return st;
-  for (auto &I : c->inst) {
+  for (auto &I : c->sh) {
     HIP_TRY(c, hipMemset(I.ms.docc, 0, sizeof(double) * I.C * NBINS));
     HIP_TRY(c, hipMemset(I.ms.gk, 0, sizeof(double) * I.C * I.ms.nbins_g * I.ms.glen));
     HIP_TRY(c, hipMemset(I.ms.count, 0, sizeof(int64_t) * I.C));
     std::vector<int64_t> ones(I.C, 1);
     HIP_TRY(c, hipMemcpy(I.ms.binsize, ones.data(), sizeof(int64_t) * I.C, hipMemcpyHostToDevice));
   }
+  HIP_TRY(c, hipDeviceSynchronize());
   return BSS_OK;
 }
-
-// checkpoint layout: magic, n_inst, then per instance: C, Lam, N, sweeps,
-// field bytes, chain stats, measurement arrays and counters
-static const uint64_t CK_MAGIC = 0x31504B4353534221ull;
 
 bss_status bss_save(bss_ctx *c, void *buf, size_t *bytes) {
   bss_status st = usable(c);
   if (st != BSS_OK) return st;
   if (!bytes) return fail(c, BSS_E_INVALID_ARG, "bytes is NULL");
   size_t need = 16;
-  for (auto &I : c->inst)
-    need += 32 + (size_t)I.C * I.Lam * I.N + sizeof(ChainStats) * I.C + sizeof(double) * I.C * NBINS +
-            sizeof(double) * I.C * I.ms.nbins_g * I.ms.glen + 2 * sizeof(int64_t) * I.C;
+  for (auto &U : c->ui) need += inst_ck_bytes(c, U);
   if (!buf) { *bytes = need; return BSS_OK; }
   if (*bytes < need) return fail(c, BSS_E_INVALID_ARG, "buffer too small");
-  for (auto &I : c->inst)
+  for (auto &I : c->sh)
     if (I.slice != 1) return fail(c, BSS_E_STATE, "save needs every instance at slice 1");
   if ((st = check_err(c)) != BSS_OK) return st;
   char *p = (char *)buf;
-  auto put = [&](const void *src, size_t n) { std::memcpy(p, src, n); p += n; };
-  uint64_t hdr[2] = {CK_MAGIC, (uint64_t)c->inst.size()};
-  put(hdr, 16);
-  for (auto &I : c->inst) {
-    int64_t meta[4] = {I.C, I.Lam, I.N, I.sweeps};
-    put(meta, 32);
-    HIP_TRY(c, hipMemcpy(p, I.h, (size_t)I.C * I.Lam * I.N, hipMemcpyDeviceToHost)); p += (size_t)I.C * I.Lam * I.N;
-    HIP_TRY(c, hipMemcpy(p, I.stats, sizeof(ChainStats) * I.C, hipMemcpyDeviceToHost)); p += sizeof(ChainStats) * I.C;
-    HIP_TRY(c, hipMemcpy(p, I.ms.docc, sizeof(double) * I.C * NBINS, hipMemcpyDeviceToHost)); p += sizeof(double) * I.C * NBINS;
-    const size_t g = sizeof(double) * I.C * I.ms.nbins_g * I.ms.glen;
-    HIP_TRY(c, hipMemcpy(p, I.ms.gk, g, hipMemcpyDeviceToHost)); p += g;
-    HIP_TRY(c, hipMemcpy(p, I.ms.count, sizeof(int64_t) * I.C, hipMemcpyDeviceToHost)); p += sizeof(int64_t) * I.C;
-    HIP_TRY(c, hipMemcpy(p, I.ms.binsize, sizeof(int64_t) * I.C, hipMemcpyDeviceToHost)); p += sizeof(int64_t) * I.C;
+  const uint64_t hdr[2] = {CK_MAGIC, (uint64_t)c->ui.size()};
+  std::memcpy(p, hdr, 16); p += 16;
+  for (auto &U : c->ui) {
+    const int64_t meta[4] = {U.C, U.Lam, U.N, c->sh[U.first].sweeps};
+    std::memcpy(p, meta, 32); p += 32;
+    if ((st = ck_transfer(c, U, p, true)) != BSS_OK) return st;
   }
   *bytes = (size_t)(p - (char *)buf);
   return BSS_OK;
@@ -875,33 +1072,45 @@ bss_status bss_load(bss_ctx *c, const void *buf, size_t bytes) {
   const char *p = (const char *)buf, *end = p + bytes;
   uint64_t hdr[2];
   std::memcpy(hdr, p, 16); p += 16;
-  if (hdr[0] != CK_MAGIC || hdr[1] != c->inst.size()) return fail(c, BSS_E_INVALID_ARG, "checkpoint does not match this context");
+  if (hdr[0] != CK_MAGIC || hdr[1] != c->ui.size()) return fail(c, BSS_E_INVALID_ARG, "checkpoint does not match this context");
+  for (auto &I : c->sh)
+    if (I.slice != 1) return fail(c, BSS_E_STATE, "load needs every instance at slice 1");
   if ((st = check_err(c)) != BSS_OK) return st;
-  for (auto &I : c->inst) {
-    if (end - p < 32) return fail(c, BSS_E_INVALID_ARG, "truncated checkpoint");
+  // validate the whole buffer before any state changes
+  {
+    const char *q = p;
+    for (auto &U : c->ui) {
+      if ((size_t)(end - q) < inst_ck_bytes(c, U)) return fail(c, BSS_E_INVALID_ARG, "truncated checkpoint");
+      int64_t meta[4];
+      std::memcpy(meta, q, 32);
+      if (meta[0] != U.C || meta[1] != U.Lam || meta[2] != U.N || meta[3] < 0)
+        return fail(c, BSS_E_INVALID_ARG, "checkpoint instance mismatch");
+      const int8_t *hf = (const int8_t *)(q + 32);
+      for (size_t e = 0; e < (size_t)U.C * U.Lam * U.N; ++e)
+        if (hf[e] != 1 && hf[e] != -1) return fail(c, BSS_E_INVALID_ARG, "corrupt field in checkpoint");
+      q += inst_ck_bytes(c, U);
+    }
+  }
+  for (auto &U : c->ui) {
     int64_t meta[4];
     std::memcpy(meta, p, 32); p += 32;
-    if (meta[0] != I.C || meta[1] != I.Lam || meta[2] != I.N) return fail(c, BSS_E_INVALID_ARG, "checkpoint instance mismatch");
-    const size_t g = sizeof(double) * I.C * I.ms.nbins_g * I.ms.glen;
-    const size_t need = (size_t)I.C * I.Lam * I.N + sizeof(ChainStats) * I.C + sizeof(double) * I.C * NBINS + g +
-                        2 * sizeof(int64_t) * I.C;
-    if ((size_t)(end - p) < need) return fail(c, BSS_E_INVALID_ARG, "truncated checkpoint");
-    const int8_t *hf = (const int8_t *)p;
-    for (size_t e = 0; e < (size_t)I.C * I.Lam * I.N; ++e)
-      if (hf[e] != 1 && hf[e] != -1) return fail(c, BSS_E_INVALID_ARG, "corrupt field in checkpoint");
-    HIP_TRY(c, hipMemcpy(I.h, p, (size_t)I.C * I.Lam * I.N, hipMemcpyHostToDevice)); p += (size_t)I.C * I.Lam * I.N;
-    HIP_TRY(c, hipMemcpy(I.stats, p, sizeof(ChainStats) * I.C, hipMemcpyHostToDevice)); p += sizeof(ChainStats) * I.C;
-    HIP_TRY(c, hipMemcpy(I.ms.docc, p, sizeof(double) * I.C * NBINS, hipMemcpyHostToDevice)); p += sizeof(double) * I.C * NBINS;
-    HIP_TRY(c, hipMemcpy(I.ms.gk, p, g, hipMemcpyHostToDevice)); p += g;
-    HIP_TRY(c, hipMemcpy(I.ms.count, p, sizeof(int64_t) * I.C, hipMemcpyHostToDevice)); p += sizeof(int64_t) * I.C;
-    HIP_TRY(c, hipMemcpy(I.ms.binsize, p, sizeof(int64_t) * I.C, hipMemcpyHostToDevice)); p += sizeof(int64_t) * I.C;
-    I.sweeps = meta[3];
-    I.slice = 1;
-    HIP_TRY(c, hipMemcpy(I.sweep_ctr, &I.sweeps, sizeof(int64_t), hipMemcpyHostToDevice));
-    Exec x{c, I, c->stream};
-    x.initialise(false);
-    if (x.e != hipSuccess) { c->poisoned = true; return fail(c, BSS_E_DEVICE, hipGetErrorString(x.e)); }
+    char *w = const_cast<char *>(p);
+    if ((st = ck_transfer(c, U, w, false)) != BSS_OK) return st;
+    p = w;
+    for (int k = 0; k < U.count; ++k) {
+      Shard &I = c->sh[U.first + k];
+      I.sweeps = meta[3];
+      I.slice = 1;
+      HIP_TRY(c, hipMemcpy(I.sweep_ctr, &I.sweeps, sizeof(int64_t), hipMemcpyHostToDevice));
+    }
   }
+  HIP_TRY(c, fork(c));
+  for (auto &I : c->sh) {
+    Exec x(c, I);
+    x.initialise(false);
+    if (x.e != hipSuccess) return exec_failed(c, x);
+  }
+  HIP_TRY(c, join(c));
   return check_err(c);
 }
 
@@ -953,9 +1162,16 @@ bss_status bss_reset_profile(bss_ctx *c) {
 void bss_destroy(bss_ctx *c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);
+  for (auto &I : c->sh) {
+    if (I.s) { hipStreamSynchronize(I.s); hipStreamDestroy(I.s); }
+    if (I.aux) { hipStreamSynchronize(I.aux); hipStreamDestroy(I.aux); }
+    if (I.ev_main) hipEventDestroy(I.ev_main);
+    if (I.ev_left) hipEventDestroy(I.ev_left);
+  }
   for (auto &f : c->fam)
     for (auto &p : f.pending) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
   for (auto e : c->pool) hipEventDestroy(e);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
   if (c->own_mem && c->mem) hipFree(c->mem);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
