@@ -67,8 +67,13 @@ typedef enum {
 
 typedef enum {
   BSS_PREC_FP64 = 0,  /* every step in FP64                                        */
-  BSS_PREC_MIXED = 1  /* FP32 G, flips, delayed updates and wraps (FP32 MFMA with
-                         FP32 accumulation); FP64 ratios, UDV/QR, recomputation    */
+  BSS_PREC_MIXED = 1  /* the last fp32_slices slices of every stabilisation block
+                         run in FP32 (G, flips, delayed updates and wraps on FP32
+                         MFMA with FP32 accumulation), the others in FP64; ratios,
+                         UDV/QR and recomputation are always FP64.  An FP32
+                         rounding error made s wraps before a recomputation is
+                         amplified by those s wraps (roughly e^{2 lambda} each), so
+                         FP32 is placed where few wraps follow.                   */
 } bss_precision;
 
 /* bss_options.flags */
@@ -89,6 +94,12 @@ typedef struct {
   double drift_abort;    /* poison the context if the wrap drift exceeds this;
                             0 = never                                              */
   int32_t trace_sweeps;  /* capacity of the record buffer, in sweeps               */
+  int32_t fp32_slices;   /* BSS_PREC_MIXED: FP32 slices at the end of each block
+                            (values >= n_stab: every slice); 0 = automatic, the
+                            largest count s whose estimated mean FP32 drift
+                            2^-24 e^{2 lambda s} stays below 1e-5 (may be 0,
+                            i.e. all FP64, at strong coupling).  Ignored in
+                            FP64 mode.                                             */
 } bss_options;
 
 /* One (L, U, t, beta, dtau) instance with its chains. */
@@ -109,11 +120,16 @@ typedef struct {
   int32_t sign;          /* product of sgn R over accepted flips (always +1 here)  */
   int32_t n_chains;
   int32_t N, Lambda, delay_k, n_stab;  /* resolved parameters                      */
+  int32_t fp32_slices;   /* resolved FP32 slices per block (0 in FP64 mode)        */
+  double drift_rel_max;  /* drift over max(1, max_ij |G_fresh|), per recomputation */
+  double drift_rel_mean;
 } bss_stats;
 
 /* Per-kernel launch timing collected under BSS_FLAG_PROFILE. */
 typedef struct {
-  char name[32];         /* kernel family: flip, wrap_gemm, gemm_f64, qr_udv, ... */
+  char name[32];         /* kernel family: flip_f32, flip_f64, wrap_f32, wrap_f64,
+                            gemm_f64, qr_udv, qr_solve, elementwise,
+                            drift_replace, measure                                */
   int64_t launches;
   double total_ms;       /* summed HIP-event durations                             */
 } bss_kernel_time;
@@ -166,6 +182,11 @@ bss_status bss_measure_double_occ(bss_ctx *c, int32_t inst, double *mean, double
 
 /* Discard accumulated measurements. */
 bss_status bss_reset_measurements(bss_ctx *c);
+
+/* Zero the per-chain counters behind bss_get_stats (proposals, acceptances,
+ * log-weight, drift); the sweep count is kept.  Lets a caller state the drift
+ * and acceptance of a stretch of sweeps, e.g. after equilibration. */
+bss_status bss_reset_stats(bss_ctx *c);
 
 /* Current equal-time Green function (positive convention) of one chain and
  * spin (0 = up, 1 = down), FP64 row-major N x N, at the current slice

@@ -22,7 +22,7 @@ FLAG_RECORD_TRACE, FLAG_REPLAY_TRACE, FLAG_NO_GRAPH, FLAG_PROFILE = 0x1, 0x2, 0x
 # every entry point declared in include/bssqmc.h
 EXPORTS = [
     "bss_options_default", "bss_create", "bss_create_batch", "bss_workspace_size", "bss_sweep",
-    "bss_step_slices", "bss_measure_gtau_k", "bss_measure_double_occ", "bss_reset_measurements",
+    "bss_step_slices", "bss_measure_gtau_k", "bss_measure_double_occ", "bss_reset_measurements", "bss_reset_stats",
     "bss_get_green", "bss_get_field", "bss_set_field", "bss_set_trace", "bss_get_trace",
     "bss_get_stats", "bss_save", "bss_load", "bss_destroy", "bss_status_string", "bss_last_error",
     "bss_get_profile", "bss_reset_profile",
@@ -33,7 +33,7 @@ class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("delay_k", ctypes.c_int32),
                 ("n_stab", ctypes.c_int32), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("flags", ctypes.c_uint32), ("drift_abort", ctypes.c_double),
-                ("trace_sweeps", ctypes.c_int32)]
+                ("trace_sweeps", ctypes.c_int32), ("fp32_slices", ctypes.c_int32)]
 
 
 class Instance(ctypes.Structure):
@@ -45,7 +45,9 @@ class Stats(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("proposals", ctypes.c_int64), ("accepted", ctypes.c_int64),
                 ("drift_max", ctypes.c_double), ("drift_mean", ctypes.c_double), ("logw", ctypes.c_double),
                 ("sign", ctypes.c_int32), ("n_chains", ctypes.c_int32), ("N", ctypes.c_int32),
-                ("Lambda", ctypes.c_int32), ("delay_k", ctypes.c_int32), ("n_stab", ctypes.c_int32)]
+                ("Lambda", ctypes.c_int32), ("delay_k", ctypes.c_int32), ("n_stab", ctypes.c_int32),
+                ("fp32_slices", ctypes.c_int32), ("drift_rel_max", ctypes.c_double),
+                ("drift_rel_mean", ctypes.c_double)]
 
 
 class KernelTime(ctypes.Structure):
@@ -81,6 +83,7 @@ def lib():
         L.bss_measure_gtau_k.argtypes = [vp, i32, vp, vp, i64]
         L.bss_measure_double_occ.argtypes = [vp, i32, P(dbl), P(dbl)]
         L.bss_reset_measurements.argtypes = [vp]
+        L.bss_reset_stats.argtypes = [vp]
         L.bss_get_green.argtypes = [vp, i32, i32, i32, vp]
         L.bss_get_field.argtypes = [vp, i32, i32, vp]
         L.bss_set_field.argtypes = [vp, i32, i32, vp]
@@ -110,12 +113,13 @@ def _ptr(a: np.ndarray):
 
 
 def make_options(precision="fp64", delay_k=0, n_stab=0, flags=0, trace_sweeps=0, drift_abort=0.0,
-                 stream=None, workspace=None, workspace_bytes=0) -> Options:
+                 stream=None, workspace=None, workspace_bytes=0, fp32_slices=0) -> Options:
     o = Options()
     lib().bss_options_default(ctypes.byref(o))
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     o.delay_k, o.n_stab, o.flags = delay_k, n_stab, flags
     o.trace_sweeps, o.drift_abort = trace_sweeps, drift_abort
+    o.fp32_slices = fp32_slices
     o.stream = stream
     o.workspace = workspace
     o.workspace_bytes = workspace_bytes
@@ -131,7 +135,7 @@ class Context:
     """
 
     def __init__(self, instances, precision="fp64", delay_k=0, n_stab=0, flags=0, trace_sweeps=0,
-                 drift_abort=0.0, stream=None):
+                 drift_abort=0.0, stream=None, fp32_slices=0):
         import torch  # device memory and streams only
 
         if not torch.cuda.is_available():
@@ -146,7 +150,7 @@ class Context:
         self.n_inst = len(instances)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         opt = make_options(precision, delay_k, n_stab, flags, trace_sweeps, drift_abort,
-                           stream=self._stream.cuda_stream)
+                           stream=self._stream.cuda_stream, fp32_slices=fp32_slices)
         nbytes = ctypes.c_size_t()
         self._check(L.bss_workspace_size(arr, len(instances), ctypes.byref(opt), ctypes.byref(nbytes)),
                     "bss_workspace_size")
@@ -160,7 +164,8 @@ class Context:
         for n in range(self.n_inst):
             st = self.stats(n)
             self._params.append(dict(N=st["N"], Lambda=st["Lambda"], delay_k=st["delay_k"], n_stab=st["n_stab"],
-                                     n_chains=st["n_chains"], L=int(instances[n]["L"])))
+                                     fp32_slices=st["fp32_slices"], n_chains=st["n_chains"],
+                                     L=int(instances[n]["L"])))
 
     # ------------------------------------------------------------------
     def _check(self, status, what):
@@ -245,6 +250,9 @@ class Context:
 
     def reset_measurements(self):
         self._check(lib().bss_reset_measurements(self._h), "bss_reset_measurements")
+
+    def reset_stats(self):
+        self._check(lib().bss_reset_stats(self._h), "bss_reset_stats")
 
     def profile(self) -> dict:
         """{kernel family: (launches, total ms)} under FLAG_PROFILE."""

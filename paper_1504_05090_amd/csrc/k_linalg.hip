@@ -171,33 +171,49 @@ __global__ void k_time_rhs(const double *DR, const double *VR, double *RHS, int 
   RHS[e] = (dr / big_part(dr)) * VR[e];
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_drift_replace(T *G, const double *Gf, int N, ChainStats *stats,
-                                                       int *err, double drift_abort, int count) {
+// drift = max_ij |G_cmp - G_fresh| over both spins of one chain, then the
+// fresh matrices are written to G_out (rounded to its type).  G_cmp and G_out
+// may be the same buffer.
+template <typename Tc, typename To>
+__global__ __launch_bounds__(256) void k_drift_replace(const Tc *Gc, To *Go, const double *Gf, int N,
+                                                       ChainStats *stats, int *err, double drift_abort,
+                                                       int count) {
   __shared__ double red[16];
   const long n = 2L * N * N, c = blockIdx.x;
-  T *g = G + c * n;
+  const Tc *gc = Gc + c * n;
+  To *go = Go + c * n;
   const double *gf = Gf + c * n;
-  double dmax = 0.0;
+  double dmax = 0.0, gmax = 0.0;
   bool bad = false;
   for (long e = threadIdx.x; e < n; e += blockDim.x) {
     const double f = gf[e];
     if (!isfinite(f)) bad = true;
-    dmax = fmax(dmax, fabs((double)g[e] - f));
-    g[e] = (T)f;
+    dmax = fmax(dmax, fabs((double)gc[e] - f));
+    gmax = fmax(gmax, fabs(f));
+    go[e] = (To)f;
   }
   const double dm = block_max(dmax, red);
+  const double gm = block_max(gmax, red);
   const double anybad = block_max(bad ? 1.0 : 0.0, red);
   if (threadIdx.x == 0) {
     if (count) {
       ChainStats *st = stats + c;
+      const double rel = dm / fmax(1.0, gm);
       st->drift_max = fmax(st->drift_max, dm);
       st->drift_sum += dm;
+      st->rdrift_max = fmax(st->rdrift_max, rel);
+      st->rdrift_sum += rel;
       st->drift_count += 1;
       if (drift_abort > 0.0 && dm > drift_abort) atomicOr(err, 2);
     }
     if (anybad > 0.0) atomicOr(err, 4);
   }
+}
+
+template <typename Ts, typename Td>
+__global__ void k_convert(const Ts *src, Td *dst, long n) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) dst[e] = (Td)src[e];
 }
 }  // namespace
 
@@ -227,14 +243,33 @@ hipError_t time_rhs(const double *DR, const double *VR, double *RHS, int mats, i
   return hipGetLastError();
 }
 
-hipError_t drift_replace(void *G, const double *Gf, int chains, int N, bool fp64, ChainStats *stats, int *err,
-                         double drift_abort, bool count, hipStream_t s) {
-  if (fp64)
-    hipLaunchKernelGGL(k_drift_replace<double>, dim3(chains), dim3(256), 0, s, (double *)G, Gf, N, stats, err,
-                       drift_abort, count ? 1 : 0);
+hipError_t drift_replace(const void *Gc, bool cmp64, void *Go, bool out64, const double *Gf, int chains, int N,
+                         ChainStats *stats, int *err, double drift_abort, bool count, hipStream_t s) {
+  const int cnt = count ? 1 : 0;
+  const dim3 g(chains), b(256);
+  if (cmp64 && out64)
+    hipLaunchKernelGGL((k_drift_replace<double, double>), g, b, 0, s, (const double *)Gc, (double *)Go, Gf, N, stats,
+                       err, drift_abort, cnt);
+  else if (cmp64)
+    hipLaunchKernelGGL((k_drift_replace<double, float>), g, b, 0, s, (const double *)Gc, (float *)Go, Gf, N, stats,
+                       err, drift_abort, cnt);
+  else if (out64)
+    hipLaunchKernelGGL((k_drift_replace<float, double>), g, b, 0, s, (const float *)Gc, (double *)Go, Gf, N, stats,
+                       err, drift_abort, cnt);
   else
-    hipLaunchKernelGGL(k_drift_replace<float>, dim3(chains), dim3(256), 0, s, (float *)G, Gf, N, stats, err,
-                       drift_abort, count ? 1 : 0);
+    hipLaunchKernelGGL((k_drift_replace<float, float>), g, b, 0, s, (const float *)Gc, (float *)Go, Gf, N, stats,
+                       err, drift_abort, cnt);
+  return hipGetLastError();
+}
+
+hipError_t convert_green(const void *src, bool src64, void *dst, bool dst64, long n, hipStream_t s) {
+  const dim3 g((unsigned)((n + 255) / 256)), b(256);
+  if (src64 && !dst64)
+    hipLaunchKernelGGL((k_convert<double, float>), g, b, 0, s, (const double *)src, (float *)dst, n);
+  else if (!src64 && dst64)
+    hipLaunchKernelGGL((k_convert<float, double>), g, b, 0, s, (const float *)src, (double *)dst, n);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ hipError_t gemm_f32(const GemmDesc &d, bool ta, bool tb, hipStream_t s);
 struct ChainStats {
   int64_t proposals, accepted;
   double logw;
-  double drift_max, drift_sum;
+  double drift_max, drift_sum;           // max_ij |G_wrapped - G_fresh|
+  double rdrift_max, rdrift_sum;         // the same over max(1, max_ij |G_fresh|)
   int64_t drift_count;
   int32_t sign, pad;
 };
@@ -85,10 +86,13 @@ hipError_t qr_solve(double *M, double *B, int mats, int N, hipStream_t s);
 hipError_t fresh_prep(const double *UR, const double *DR, const double *VR, double *W1,
                       const double *W2, const double *DL, double *RHS, int mats, int N,
                       hipStream_t s);
-// drift = max |G - Gf| per chain; G <- Gf (bulk rounding)
-hipError_t drift_replace(void *G, const double *Gf, int chains, int N, bool fp64,
-                         ChainStats *stats, int *err, double drift_abort, bool count,
-                         hipStream_t s);
+// drift = max |G_cmp - Gf| per chain; G_out <- Gf (rounded to G_out's type);
+// cmp64 / out64 select FP64 or FP32 for G_cmp / G_out
+hipError_t drift_replace(const void *Gcmp, bool cmp64, void *Gout, bool out64, const double *Gf,
+                         int chains, int N, ChainStats *stats, int *err, double drift_abort,
+                         bool count, hipStream_t s);
+// dst <- src between FP64 and FP32 Green-function stacks (n elements)
+hipError_t convert_green(const void *src, bool src64, void *dst, bool dst64, long n, hipStream_t s);
 // RHS = Ds_R V_R (right-hand side of the time-displaced G(tau_l, 0) system)
 hipError_t time_rhs(const double *DR, const double *VR, double *RHS, int mats, int N, hipStream_t s);
 // reciprocal of the big parts of D (for the final left product)

@@ -2,17 +2,18 @@
 // memory layout, the per-slice launch schedule, stabilisation bookkeeping,
 // measurement, trace record/replay, checkpoints and the C ABI of bssqmc.h.
 //
-// Scheduling.  The chains of an instance are split into shards, contiguous
-// chain ranges with their own device state and their own pair of HIP streams
-// (main, aux).  The flip kernel of a slice occupies one CU per chain and is
-// latency bound, so the shards' launch sequences are interleaved slice by
-// slice and the hardware overlaps one shard's flips with another shard's
-// GEMMs and QRs.  The left-stack rebuild at the end of a sweep depends only on
-// that sweep's block products: it runs on the aux stream, and the next sweep
-// waits for it only at its first recomputation.  Every enqueuing call forks
-// from the context stream and joins back into it, so the caller sees a
-// single asynchronous stream.  Sharding changes no result: random numbers
-// and the accept history are keyed by the chain's index in its instance.
+// Scheduling.  Device state is organised in shards: contiguous chain ranges
+// of one instance (by default all its chains), each with its own pair of HIP
+// streams (main, aux).  A sweep issues the shards' launch sequences slice by
+// slice in turn, so the instances of a batch run concurrently and small
+// instances fill the CUs that a large one leaves idle during its
+// latency-bound flip phase.  The left-stack rebuild at the end of a sweep
+// depends only on that sweep's block products: it runs on the aux stream, and
+// the next sweep waits for it only at its first recomputation.  Every
+// enqueuing call forks from the context stream and joins back into it, so the
+// caller sees a single asynchronous stream.  Sharding changes no result:
+// random numbers and the accept history are keyed by the chain's index in its
+// instance.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -53,13 +54,16 @@ struct Carver {
 struct Shard {
   // parameters
   int L = 0, N = 0, Lam = 0, C = 0, mats = 0, k = 1, n_stab = 1, nb = 1;
+  int m32 = 0;                           // FP32 slices at the end of each block (mixed mode)
   int inst = 0, chain0 = 0, Ctot = 0;
   double U = 0, t = 0, beta = 0, dtau = 0, lambda = 0;
   uint64_t seed = 0;
-  // device state (bulk = FP32 in mixed mode, FP64 otherwise)
+  // device state
   double *Em = nullptr, *Ep = nullptr;   // e^{-dtau K}, e^{+dtau K}
-  void *Etm = nullptr, *Etp = nullptr;   // bulk copies
-  void *G = nullptr, *Tw = nullptr, *dv = nullptr;
+  float *Etm = nullptr, *Etp = nullptr;  // FP32 copies (mixed mode)
+  double *G64 = nullptr;                 // G [2C][N][N] while an FP64 slice is current
+  float *G32 = nullptr;                  // G [2C][N][N] while an FP32 slice is current (mixed mode)
+  void *Tw = nullptr, *dv = nullptr;     // wrap temporary, slice diagonals: sized for FP64
   int8_t *h = nullptr;
   double *dvD = nullptr;                 // [mats][n_stab][N]
   double *Pc = nullptr, *Pw = nullptr;   // block products [nb][mats][N^2]
@@ -75,6 +79,7 @@ struct Shard {
   hipStream_t s = nullptr, aux = nullptr;
   hipEvent_t ev_main = nullptr, ev_left = nullptr;
   bool left_pending = false;             // a left rebuild on aux not yet waited for by s
+  bool cur64 = true;                     // G64 (true) or G32 holds the current G
   int slice = 1;
   int64_t sweeps = 0;
 };
@@ -120,9 +125,10 @@ struct bss_ctx {
 };
 
 namespace {
-enum KFam { F_FLIP, F_WRAP, F_GEMM64, F_QR_UDV, F_QR_SOLVE, F_ELEM, F_DRIFT, F_MEAS, F_COUNT };
-const char *const FAM_NAMES[F_COUNT] = {"flip", "wrap_gemm", "gemm_f64", "qr_udv", "qr_solve", "elementwise",
-                                        "drift_replace", "measure"};
+enum KFam { F_FLIP32, F_FLIP64, F_WRAP32, F_WRAP64, F_GEMM64, F_QR_UDV, F_QR_SOLVE, F_ELEM, F_DRIFT, F_MEAS,
+            F_COUNT };
+const char *const FAM_NAMES[F_COUNT] = {"flip_f32", "flip_f64", "wrap_f32", "wrap_f64", "gemm_f64", "qr_udv",
+                                        "qr_solve", "elementwise", "drift_replace", "measure"};
 
 hipEvent_t take_event(bss_ctx *c) {
   if (!c->pool.empty()) { hipEvent_t e = c->pool.back(); c->pool.pop_back(); return e; }
@@ -189,10 +195,24 @@ int auto_nstab(double U, double dtau) {
   return std::max(1, std::min(n, 10));
 }
 
-// Shards per instance: two once each half still fills the GEMMs of a slice
-// (the environment variable BSS_SHARDS = 1..8 overrides, for tuning).
+// FP32 slices per block in mixed mode when the caller leaves it open: an
+// FP32 rounding error (2^-24 relative) made s wraps before a recomputation
+// grows by about e^{2 lambda} per wrap (the spread of the slice's diagonal
+// factors), so take the largest s with 2^-24 e^{2 lambda s} <= 1e-5, an
+// estimate of the mean relative drift the FP32 slices add.
+int auto_fp32_slices(double lambda, int n_stab) {
+  const double budget = std::log(1e-5 * 16777216.0);
+  if (lambda <= 0.0) return n_stab;
+  const int s = (int)std::floor(budget / (2.0 * lambda));
+  return std::max(0, std::min(s, n_stab));
+}
+
+// Shards per instance: one by default -- two shards of the 16 x 16, 128-chain
+// sweep measured within 2% of one, since the GEMMs and QRs of one shard
+// already fill the chip (the environment variable BSS_SHARDS = 1..8
+// overrides, for tuning).
 int shard_count(int C) {
-  int s = C >= 32 ? 2 : 1;
+  int s = 1;
   if (const char *env = std::getenv("BSS_SHARDS")) {
     const int v = std::atoi(env);
     if (v >= 1 && v <= 8) s = v;
@@ -201,14 +221,14 @@ int shard_count(int C) {
 }
 
 void layout_shard(Shard &I, bool fp64, Carver &cv) {
-  const size_t NN = nn(I), M = (size_t)I.mats, bsz = fp64 ? 8 : 4;
+  const size_t NN = nn(I), M = (size_t)I.mats;
   I.Em = cv.take<double>(NN);
   I.Ep = cv.take<double>(NN);
-  if (!fp64) { I.Etm = cv.take<char>(NN * bsz); I.Etp = cv.take<char>(NN * bsz); }
-  else { I.Etm = I.Em; I.Etp = I.Ep; }
-  I.G = cv.take<char>(M * NN * bsz);
-  I.Tw = cv.take<char>(M * NN * bsz);
-  I.dv = cv.take<char>(M * 2 * I.N * bsz);
+  if (!fp64) { I.Etm = cv.take<float>(NN); I.Etp = cv.take<float>(NN); }
+  I.G64 = cv.take<double>(M * NN);
+  if (!fp64) I.G32 = cv.take<float>(M * NN);
+  I.Tw = cv.take<double>(M * NN);
+  I.dv = cv.take<double>(M * 2 * I.N);
   I.h = cv.take<int8_t>((size_t)I.C * I.Lam * I.N);
   I.dvD = cv.take<double>(M * I.n_stab * I.N);
   I.Pc = cv.take<double>((size_t)I.nb * M * NN);
@@ -260,6 +280,8 @@ bool resolve(const bss_instance *in, int n, const bss_options &opt, std::vector<
     I.n_stab = opt.n_stab > 0 ? opt.n_stab : auto_nstab(I.U, I.dtau);
     I.n_stab = std::min(I.n_stab, I.Lam);
     I.nb = (I.Lam + I.n_stab - 1) / I.n_stab;
+    if (opt.precision == BSS_PREC_MIXED)
+      I.m32 = opt.fp32_slices > 0 ? std::min(opt.fp32_slices, I.n_stab) : auto_fp32_slices(I.lambda, I.n_stab);
     UInst U;
     U.first = (int)out.size();
     U.C = I.Ctot; U.N = I.N; U.Lam = I.Lam;
@@ -287,6 +309,7 @@ bool check_options(const bss_options *o, std::string &why) {
   if ((o->flags & BSS_FLAG_RECORD_TRACE) && (o->flags & BSS_FLAG_REPLAY_TRACE)) { why = "record and replay are exclusive"; return false; }
   if ((o->flags & BSS_FLAG_RECORD_TRACE) && o->trace_sweeps < 1) { why = "trace_sweeps must be >= 1 to record"; return false; }
   if (o->trace_sweeps < 0) { why = "trace_sweeps must be >= 0"; return false; }
+  if (o->fp32_slices < 0) { why = "fp32_slices must be >= 0"; return false; }
   if (!(o->drift_abort >= 0.0)) { why = "drift_abort must be >= 0"; return false; }
   return true;
 }
@@ -336,6 +359,31 @@ struct Exec {
   double *LU(int b) const { return I.LU + (size_t)b * I.mats * NN(); }
   double *LD(int b) const { return I.LD + (size_t)b * I.mats * I.N; }
   double *LV(int b) const { return I.LV + (size_t)b * I.mats * NN(); }
+
+  // slice l runs in FP32 iff it is among the last m32 slices of its block
+  bool fp32_at(int l) const {
+    if (I.m32 <= 0) return false;
+    const int end = std::min(((l - 1) / I.n_stab + 1) * I.n_stab, I.Lam);
+    return end - l < I.m32;
+  }
+  void *Gcur() const { return I.cur64 ? (void *)I.G64 : (void *)I.G32; }
+  // the current G in the precision slice l needs (FP64 -> FP32 inside a block)
+  void use_precision(int l) {
+    const bool want64 = !fp32_at(l);
+    if (want64 == I.cur64) return;
+    Timed tm(c, F_ELEM, s);
+    chk(convert_green(Gcur(), I.cur64, want64 ? (void *)I.G64 : (void *)I.G32, want64, (long)I.mats * NN(), s));
+    I.cur64 = want64;
+  }
+  // fresh G from Gf into the precision of slice `next`, with the drift
+  // against the current G recorded when `count`
+  void replace(int next, bool count, double abort_at) {
+    const bool out64 = !fp32_at(next);
+    Timed tm(c, F_DRIFT, s);
+    chk(drift_replace(Gcur(), I.cur64, out64 ? (void *)I.G64 : (void *)I.G32, out64, I.Gf, I.C, I.N, I.stats,
+                      c->err, abort_at, count, s));
+    I.cur64 = out64;
+  }
 
   // the main stream waits for an outstanding left rebuild before it touches
   // the left factors, the block products or the QR scratch
@@ -430,15 +478,16 @@ struct Exec {
       right_update(b);
     }
     fresh(I.nb - 1, false, I.Gf);
-    chk(drift_replace(I.G, I.Gf, I.C, I.N, c->fp64, I.stats, c->err, 0.0, false, s));
+    replace(I.slice, false, 0.0);
     left_rebuild();
   }
 
   void flip(int l) {
+    use_precision(l);
     FlipArgs a{};
     a.N = I.N; a.Lam = I.Lam; a.l = l; a.k = I.k; a.chains = I.C;
     a.chain0 = I.chain0; a.chains_total = I.Ctot;
-    a.G = I.G; a.h = I.h; a.dv = I.dv;
+    a.G = Gcur(); a.h = I.h; a.dv = I.dv;
     a.dlt_up_p = std::exp(-2.0 * I.lambda) - 1.0;   // sigma = +1, h = +1
     a.dlt_up_m = std::exp(2.0 * I.lambda) - 1.0;    // sigma = +1, h = -1
     a.dlt_dn_p = std::exp(2.0 * I.lambda) - 1.0;    // sigma = -1, h = +1
@@ -449,27 +498,29 @@ struct Exec {
     a.trace_mode = (c->opt.flags & BSS_FLAG_RECORD_TRACE) ? 1 : ((c->opt.flags & BSS_FLAG_REPLAY_TRACE) ? 2 : 0);
     a.trace = U.trace; a.trace_base = U.trace_base; a.trace_sweeps = U.trace_cap;
     a.stats = I.stats; a.err = c->err;
-    Timed tm(c, F_FLIP, s);
-    chk(flip_slice(a, c->fp64, s));
+    Timed tm(c, I.cur64 ? F_FLIP64 : F_FLIP32, s);
+    chk(flip_slice(a, I.cur64, s));
   }
 
+  // G <- e^{-dtau K} (D G D^{-1}) e^{+dtau K} in the current G's precision
   void wrap() {
+    const bool f64 = I.cur64;
     const long bs = (long)NN();
     GemmDesc d = gemm_desc(I.N, I.mats);
     // T = (D G D^{-1}) e^{+dtau K}
-    d.A = I.G; d.sA = bs; d.B = I.Etp; d.sB = 0; d.C = I.Tw; d.sC = bs;
-    const size_t esz = c->fp64 ? 8 : 4;
+    d.A = Gcur(); d.sA = bs; d.B = f64 ? (void *)I.Ep : (void *)I.Etp; d.sB = 0; d.C = I.Tw; d.sC = bs;
+    const size_t esz = f64 ? 8 : 4;
     d.rs = I.dv; d.srs = 2L * I.N;
     d.ks = (char *)I.dv + esz * I.N; d.sks = 2L * I.N;
     {
-      Timed tm(c, F_WRAP, s);
-      chk(c->fp64 ? gemm_f64(d, false, false, s) : gemm_f32(d, false, false, s));
+      Timed tm(c, f64 ? F_WRAP64 : F_WRAP32, s);
+      chk(f64 ? gemm_f64(d, false, false, s) : gemm_f32(d, false, false, s));
     }
     // G = e^{-dtau K} T
     GemmDesc d2 = gemm_desc(I.N, I.mats);
-    d2.A = I.Etm; d2.sA = 0; d2.B = I.Tw; d2.sB = bs; d2.C = I.G; d2.sC = bs;
-    Timed tm(c, F_WRAP, s);
-    chk(c->fp64 ? gemm_f64(d2, false, false, s) : gemm_f32(d2, false, false, s));
+    d2.A = f64 ? (void *)I.Em : (void *)I.Etm; d2.sA = 0; d2.B = I.Tw; d2.sB = bs; d2.C = Gcur(); d2.sC = bs;
+    Timed tm(c, f64 ? F_WRAP64 : F_WRAP32, s);
+    chk(f64 ? gemm_f64(d2, false, false, s) : gemm_f32(d2, false, false, s));
   }
 
   void stabilise(int l) {
@@ -478,8 +529,7 @@ struct Exec {
     block_product(b);
     right_update(b);
     fresh(b, false, I.Gf);
-    Timed tm(c, F_DRIFT, s);
-    chk(drift_replace(I.G, I.Gf, I.C, I.N, c->fp64, I.stats, c->err, c->opt.drift_abort, true, s));
+    replace(l == I.Lam ? 1 : l + 1, true, c->opt.drift_abort);
   }
 
   void slice(int l) {
@@ -632,8 +682,7 @@ bss_status create_impl(const bss_instance *in, int n, const bss_options *opt_in,
   if (fork(c) != hipSuccess) return bail(BSS_E_DEVICE);
   for (auto &I : c->sh) {
     Exec x(c, I);
-    x.chk(build_exp(I.L, I.t, I.dtau, I.Em, I.Ep, c->fp64 ? nullptr : I.Etm, c->fp64 ? nullptr : I.Etp, c->fp64,
-                    I.s));
+    x.chk(build_exp(I.L, I.t, I.dtau, I.Em, I.Ep, I.Etm, I.Etp, c->fp64, I.s));
     x.initialise(true);
     if (x.e != hipSuccess) { c->last_error = hipGetErrorString(x.e); return bail(BSS_E_DEVICE); }
   }
@@ -777,11 +826,11 @@ bss_status bss_get_green(bss_ctx *c, int32_t inst, int32_t chain, int32_t spin, 
   Shard &I = shard_of(c, *U, chain);
   const size_t n = nn(I);
   const size_t off = (size_t)(2 * (chain - I.chain0) + spin) * n;
-  if (c->fp64) {
-    HIP_TRY(c, hipMemcpy(out, (double *)I.G + off, sizeof(double) * n, hipMemcpyDeviceToHost));
+  if (I.cur64) {
+    HIP_TRY(c, hipMemcpy(out, I.G64 + off, sizeof(double) * n, hipMemcpyDeviceToHost));
   } else {
     std::vector<float> tmp(n);
-    HIP_TRY(c, hipMemcpy(tmp.data(), (float *)I.G + off, sizeof(float) * n, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(tmp.data(), I.G32 + off, sizeof(float) * n, hipMemcpyDeviceToHost));
     for (size_t e = 0; e < n; ++e) out[e] = tmp[e];
   }
   return BSS_OK;
@@ -857,7 +906,7 @@ bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
   if ((st = check_err(c)) != BSS_OK) return st;
   std::memset(out, 0, sizeof(*out));
   out->sign = 1;
-  double dsum = 0;
+  double dsum = 0, rsum = 0;
   int64_t dcnt = 0;
   for (int k = 0; k < U->count; ++k) {
     const Shard &I = c->sh[U->first + k];
@@ -868,13 +917,17 @@ bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
       out->accepted += x.accepted;
       out->logw += x.logw;
       out->drift_max = std::max(out->drift_max, x.drift_max);
+      out->drift_rel_max = std::max(out->drift_rel_max, x.rdrift_max);
       dsum += x.drift_sum;
+      rsum += x.rdrift_sum;
       dcnt += x.drift_count;
     }
     out->sweeps = I.sweeps;
     out->N = I.N; out->Lambda = I.Lam; out->delay_k = I.k; out->n_stab = I.n_stab;
+    out->fp32_slices = I.m32;
   }
   out->drift_mean = dcnt ? dsum / dcnt : 0.0;
+  out->drift_rel_mean = dcnt ? rsum / dcnt : 0.0;
   out->n_chains = U->C;
   return BSS_OK;
 }
@@ -982,7 +1035,7 @@ bss_status measure_common(bss_ctx *c, int32_t inst, bool gk_wanted, double *mean
 // the chain statistics, the double-occupancy bins, the G(tau,k) bins, the
 // measurement counts and the bin sizes.  The layout does not depend on how
 // the chains are sharded.
-const uint64_t CK_MAGIC = 0x31504B4353534221ull;
+const uint64_t CK_MAGIC = 0x32504B4353534221ull;
 
 size_t inst_ck_bytes(const bss_ctx *c, const UInst &U) {
   const Shard &F = c->sh[U.first];
@@ -1039,6 +1092,18 @@ bss_status bss_reset_measurements(bss_ctx *c) {
     HIP_TRY(c, hipMemcpy(I.ms.binsize, ones.data(), sizeof(int64_t) * I.C, hipMemcpyHostToDevice));
   }
   HIP_TRY(c, hipDeviceSynchronize());
+  return BSS_OK;
+}
+
+bss_status bss_reset_stats(bss_ctx *c) {
+  bss_status st = usable(c);
+  if (st != BSS_OK) return st;
+  if ((st = check_err(c)) != BSS_OK) return st;
+  for (auto &I : c->sh) {
+    std::vector<ChainStats> zero(I.C);
+    std::memset(zero.data(), 0, sizeof(ChainStats) * I.C);
+    HIP_TRY(c, hipMemcpy(I.stats, zero.data(), sizeof(ChainStats) * I.C, hipMemcpyHostToDevice));
+  }
   return BSS_OK;
 }
 
