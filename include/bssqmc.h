@@ -79,7 +79,10 @@ typedef enum {
 /* bss_options.flags */
 #define BSS_FLAG_RECORD_TRACE 0x1u /* record accept decisions (see bss_get_trace)     */
 #define BSS_FLAG_REPLAY_TRACE 0x2u /* take accept decisions from bss_set_trace        */
-#define BSS_FLAG_NO_GRAPH 0x4u     /* launch kernels directly instead of a hipGraph   */
+#define BSS_FLAG_NO_GRAPH 0x4u     /* bss_sweep launches kernels directly; by default
+                                      it captures one unmeasured sweep into a
+                                      hipGraph on first use and replays it (measured
+                                      sweeps and PROFILE launch directly)            */
 #define BSS_FLAG_PROFILE 0x8u      /* time every kernel launch with HIP events        */
 
 typedef struct {
@@ -123,6 +126,7 @@ typedef struct {
   int32_t fp32_slices;   /* resolved FP32 slices per block (0 in FP64 mode)        */
   double drift_rel_max;  /* drift over max(1, max_ij |G_fresh|), per recomputation */
   double drift_rel_mean;
+  int32_t sweep_graph;   /* 1 once bss_sweep replays a captured hipGraph          */
 } bss_stats;
 
 /* Per-kernel launch timing collected under BSS_FLAG_PROFILE. */
@@ -182,6 +186,10 @@ bss_status bss_measure_double_occ(bss_ctx *c, int32_t inst, double *mean, double
 
 /* Discard accumulated measurements. */
 bss_status bss_reset_measurements(bss_ctx *c);
+
+/* Wait until all work enqueued on the context has finished; returns the
+ * status of any failure the device flagged meanwhile (as bss_get_* would). */
+bss_status bss_synchronize(bss_ctx *c);
 
 /* Zero the per-chain counters behind bss_get_stats (proposals, acceptances,
  * log-weight, drift); the sweep count is kept.  Lets a caller state the drift

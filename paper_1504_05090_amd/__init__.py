@@ -22,7 +22,7 @@ FLAG_RECORD_TRACE, FLAG_REPLAY_TRACE, FLAG_NO_GRAPH, FLAG_PROFILE = 0x1, 0x2, 0x
 # every entry point declared in include/bssqmc.h
 EXPORTS = [
     "bss_options_default", "bss_create", "bss_create_batch", "bss_workspace_size", "bss_sweep",
-    "bss_step_slices", "bss_measure_gtau_k", "bss_measure_double_occ", "bss_reset_measurements", "bss_reset_stats",
+    "bss_step_slices", "bss_measure_gtau_k", "bss_measure_double_occ", "bss_reset_measurements", "bss_reset_stats", "bss_synchronize",
     "bss_get_green", "bss_get_field", "bss_set_field", "bss_set_trace", "bss_get_trace",
     "bss_get_stats", "bss_save", "bss_load", "bss_destroy", "bss_status_string", "bss_last_error",
     "bss_get_profile", "bss_reset_profile",
@@ -47,7 +47,7 @@ class Stats(ctypes.Structure):
                 ("sign", ctypes.c_int32), ("n_chains", ctypes.c_int32), ("N", ctypes.c_int32),
                 ("Lambda", ctypes.c_int32), ("delay_k", ctypes.c_int32), ("n_stab", ctypes.c_int32),
                 ("fp32_slices", ctypes.c_int32), ("drift_rel_max", ctypes.c_double),
-                ("drift_rel_mean", ctypes.c_double)]
+                ("drift_rel_mean", ctypes.c_double), ("sweep_graph", ctypes.c_int32)]
 
 
 class KernelTime(ctypes.Structure):
@@ -84,6 +84,7 @@ def lib():
         L.bss_measure_double_occ.argtypes = [vp, i32, P(dbl), P(dbl)]
         L.bss_reset_measurements.argtypes = [vp]
         L.bss_reset_stats.argtypes = [vp]
+        L.bss_synchronize.argtypes = [vp]
         L.bss_get_green.argtypes = [vp, i32, i32, i32, vp]
         L.bss_get_field.argtypes = [vp, i32, i32, vp]
         L.bss_set_field.argtypes = [vp, i32, i32, vp]
@@ -200,7 +201,8 @@ class Context:
         self._check(lib().bss_step_slices(self._h, n), "bss_step_slices")
 
     def synchronize(self):
-        self._stream.synchronize()
+        """Wait for the context's work (on its own stream or the caller's)."""
+        self._check(lib().bss_synchronize(self._h), "bss_synchronize")
 
     def green(self, inst=0, chain=0, spin=0) -> np.ndarray:
         N = self._params[inst]["N"]

@@ -6,8 +6,7 @@
 // WM x WN quadrant of (WM/16) x (WN/16) MFMA blocks.  K advances in chunks of
 // BK through a double-buffered LDS stage: the next chunk is fetched from
 // global memory into registers while the current one feeds the MFMAs, so a
-// chunk costs one barrier.  Operands are stored k-major in LDS so that the
-// 16 lanes of an MFMA operand read 16 consecutive words.  Optional diagonal
+// chunk costs one barrier.  Optional diagonal
 // scalings (of A's columns, of the result's rows and columns) are fused into
 // the A fetch and the epilogue.
 #include "common.h"
@@ -17,14 +16,24 @@ namespace bss {
 
 namespace {
 
+// LDS layouts.  An operand whose global rows run along k (A not transposed,
+// B transposed) is staged k-contiguous, [m or n][BK + KP], and one whose rows
+// run along m / n is staged [BK][BM or BN + 16]; either way a fetch writes
+// consecutive words from consecutive lanes.  The pads make the MFMA operand
+// reads (16 lanes along m or n times 4 lanes along k) hit distinct banks:
+// KP = 4 words for FP32 and 2 doubles for FP64 spread the 16 rows of a
+// k-contiguous tile over all banks; 16 elements shift the 4 k-rows of an
+// m-contiguous tile by a quarter (FP32) or a half (FP64) of the 64 banks.
 template <typename T, bool TA, bool TB, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
   constexpr int WM = BM / 2, WN = BN / 2;          // 2 x 2 wavefronts
   constexpr int TM = WM / 16, TN = WN / 16;        // MFMA blocks per wavefront
-  constexpr int PA = BM + 4, PB = BN + 4;          // padded LDS row lengths
+  constexpr int KP = sizeof(T) == 4 ? 4 : 2;
+  constexpr int A_ROWS = TA ? BK : BM, A_LD = TA ? BM + 16 : BK + KP;
+  constexpr int B_ROWS = TB ? BN : BK, B_LD = TB ? BK + KP : BN + 16;
   constexpr int EA = BM * BK / 256, EB = BK * BN / 256;   // elements per thread per chunk
-  __shared__ T As[2][BK][PA];
-  __shared__ T Bs[2][BK][PB];
+  __shared__ T As[2][A_ROWS][A_LD];
+  __shared__ T Bs[2][B_ROWS][B_LD];
 
   const int tilesN = (d.N + BN - 1) / BN;
   const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
@@ -49,6 +58,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
     const int idx = e * 256 + t;
     if (!TB) { kk = idx / BN; jj = idx % BN; } else { jj = idx / BK; kk = idx % BK; }
   };
+  auto a_lds = [&](int buf, int ii, int kk) -> T & { return TA ? As[buf][kk][ii] : As[buf][ii][kk]; };
+  auto b_lds = [&](int buf, int kk, int jj) -> T & { return TB ? Bs[buf][jj][kk] : Bs[buf][kk][jj]; };
   T ra[EA], rb[EB];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -78,13 +89,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
     for (int e = 0; e < EA; ++e) {
       int ii, kk;
       a_index(e, ii, kk);
-      As[buf][kk][ii] = ra[e];
+      a_lds(buf, ii, kk) = ra[e];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       int kk, jj;
       b_index(e, kk, jj);
-      Bs[buf][kk][jj] = rb[e];
+      b_lds(buf, kk, jj) = rb[e];
     }
   };
 
@@ -106,9 +117,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
     for (int kk = 0; kk < BK; kk += 4) {
       T av[TM], bv[TN];
 #pragma unroll
-      for (int a = 0; a < TM; ++a) av[a] = As[buf][kk + lq][wr * WM + a * 16 + l16];
+      for (int a = 0; a < TM; ++a) av[a] = a_lds(buf, wr * WM + a * 16 + l16, kk + lq);
 #pragma unroll
-      for (int c = 0; c < TN; ++c) bv[c] = Bs[buf][kk + lq][wc * WN + c * 16 + l16];
+      for (int c = 0; c < TN; ++c) bv[c] = b_lds(buf, kk + lq, wc * WN + c * 16 + l16);
 #pragma unroll
       for (int a = 0; a < TM; ++a)
 #pragma unroll

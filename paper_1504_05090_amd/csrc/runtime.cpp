@@ -95,6 +95,13 @@ struct UInst {
 
 size_t nn(const Shard &I) { return (size_t)I.N * I.N; }
 
+// slice l runs in FP32 iff it is among the last m32 slices of its block
+bool fp32_slice(const Shard &I, int l) {
+  if (I.m32 <= 0) return false;
+  const int end = std::min(((l - 1) / I.n_stab + 1) * I.n_stab, I.Lam);
+  return end - l < I.m32;
+}
+
 }  // namespace
 
 struct bss_ctx {
@@ -122,6 +129,9 @@ struct bss_ctx {
   };
   std::vector<Fam> fam;
   std::vector<hipEvent_t> pool;
+  // one captured (unmeasured) sweep, replayed by bss_sweep
+  hipGraphExec_t sweep_graph = nullptr;
+  bool graphs = false;   // capture and replay sweeps (off: NO_GRAPH, PROFILE, or capture failed)
 };
 
 namespace {
@@ -360,12 +370,7 @@ struct Exec {
   double *LD(int b) const { return I.LD + (size_t)b * I.mats * I.N; }
   double *LV(int b) const { return I.LV + (size_t)b * I.mats * NN(); }
 
-  // slice l runs in FP32 iff it is among the last m32 slices of its block
-  bool fp32_at(int l) const {
-    if (I.m32 <= 0) return false;
-    const int end = std::min(((l - 1) / I.n_stab + 1) * I.n_stab, I.Lam);
-    return end - l < I.m32;
-  }
+  bool fp32_at(int l) const { return fp32_slice(I, l); }
   void *Gcur() const { return I.cur64 ? (void *)I.G64 : (void *)I.G32; }
   // the current G in the precision slice l needs (FP64 -> FP32 inside a block)
   void use_precision(int l) {
@@ -671,6 +676,7 @@ bss_status create_impl(const bss_instance *in, int n, const bss_options *opt_in,
   cv.base = c->mem;
   layout_all(c->sh, c->ui, opt, cv, &c->err);
   c->profile = (opt.flags & BSS_FLAG_PROFILE) != 0;   // creation work is dropped from the profile below
+  c->graphs = !c->profile && !(opt.flags & BSS_FLAG_NO_GRAPH);
   hipStream_t s = c->stream;
   if (hipMemsetAsync(c->mem, 0, cv.off, s) != hipSuccess) return bail(BSS_E_DEVICE);
   if (hipStreamSynchronize(s) != hipSuccess) return bail(BSS_E_DEVICE);
@@ -734,13 +740,15 @@ bss_status bss_workspace_size(const bss_instance *inst, int32_t n_inst, const bs
   return BSS_OK;
 }
 
-bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure) {
-  bss_status st = usable(c);
-  if (st != BSS_OK) return st;
-  if (n_sweeps < 0) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be >= 0");
-  for (auto &I : c->sh)
-    if (I.slice != 1) return fail(c, BSS_E_STATE, "an instance is part-way through a sweep");
-  if (n_sweeps == 0) return BSS_OK;
+}  // extern "C"
+
+namespace {
+
+// Enqueue n whole sweeps (every shard at slice 1) between a fork from and a
+// join into the context stream.  The host-side state it leaves (slice 1, the
+// precision of slice 1, a pending left rebuild) is the same after every
+// sweep, which is what lets one captured sweep stand for any of them.
+bss_status enqueue_sweeps(bss_ctx *c, int n_sweeps, bool measure) {
   HIP_TRY(c, fork(c));
   int lam_max = 0;
   for (auto &I : c->sh) lam_max = std::max(lam_max, I.Lam);
@@ -757,12 +765,78 @@ bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure) {
       }
     if (measure)
       for (auto &x : xs) x.measure();
-    for (auto &x : xs) {
+    for (auto &x : xs)
       if (x.e != hipSuccess) return exec_failed(c, x);
-      x.I.sweeps += 1;
-    }
   }
   HIP_TRY(c, join(c));
+  return BSS_OK;
+}
+
+// Capture one unmeasured sweep into an executable graph.  The capture starts
+// from the context stream with nothing pending on the shard streams: launches
+// of the graph are ordered on that stream, so each replay begins after the
+// previous one (left rebuild included) has finished.  Returns false if the
+// runtime refuses the capture; the caller then stays with direct launches.
+// Measured sweeps are not captured: capturing one crashed the host process
+// inside the HIP runtime, so they always launch directly.
+bool capture_sweep(bss_ctx *c) {
+  std::vector<bool> pend(c->sh.size());
+  std::vector<bool> cur(c->sh.size());
+  for (size_t i = 0; i < c->sh.size(); ++i) {
+    pend[i] = c->sh[i].left_pending;
+    cur[i] = c->sh[i].cur64;
+    c->sh[i].left_pending = false;
+  }
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    const bss_status st = enqueue_sweeps(c, 1, false);
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    ok = st == BSS_OK && e == hipSuccess && g != nullptr;
+  }
+  hipGraphExec_t ex = nullptr;
+  if (ok) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) hipGraphDestroy(g);
+  // a capture enqueues nothing: restore the host-side state it advanced
+  for (size_t i = 0; i < c->sh.size(); ++i) {
+    c->sh[i].left_pending = pend[i];
+    c->sh[i].cur64 = cur[i];
+  }
+  c->poisoned = false;
+  (void)hipGetLastError();
+  if (!ok) {
+    if (ex) hipGraphExecDestroy(ex);
+    return false;
+  }
+  c->sweep_graph = ex;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure) {
+  bss_status st = usable(c);
+  if (st != BSS_OK) return st;
+  if (n_sweeps < 0) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be >= 0");
+  for (auto &I : c->sh)
+    if (I.slice != 1) return fail(c, BSS_E_STATE, "an instance is part-way through a sweep");
+  if (n_sweeps == 0) return BSS_OK;
+  const bool replay = c->graphs && !measure;
+  if (replay && !c->sweep_graph && !capture_sweep(c)) c->graphs = false;
+  if (replay && c->graphs) {
+    for (int sw = 0; sw < n_sweeps; ++sw) HIP_TRY(c, hipGraphLaunch(c->sweep_graph, c->stream));
+    // the replays leave what direct launches would: slice 1 in its
+    // precision, every left rebuild waited for on the context stream
+    for (auto &I : c->sh) {
+      I.cur64 = !fp32_slice(I, 1);
+      I.left_pending = false;
+    }
+  } else if ((st = enqueue_sweeps(c, n_sweeps, measure != 0)) != BSS_OK) {
+    return st;
+  }
+  for (auto &I : c->sh) I.sweeps += n_sweeps;
   return BSS_OK;
 }
 
@@ -883,6 +957,11 @@ bss_status bss_set_trace(bss_ctx *c, int32_t inst, const uint8_t *accept, int32_
   int64_t base = c->sh[U->first].sweeps;
   HIP_TRY(c, hipMemcpy(U->trace_base, &base, sizeof(base), hipMemcpyHostToDevice));
   U->trace_cap = n_sweeps;   // sweeping past this window is an error
+  // the flip launches carry the window length: captured sweeps are stale
+  if (c->sweep_graph) {
+    hipGraphExecDestroy(c->sweep_graph);
+    c->sweep_graph = nullptr;
+  }
   return BSS_OK;
 }
 
@@ -928,6 +1007,7 @@ bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
   }
   out->drift_mean = dcnt ? dsum / dcnt : 0.0;
   out->drift_rel_mean = dcnt ? rsum / dcnt : 0.0;
+  out->sweep_graph = c->sweep_graph ? 1 : 0;
   out->n_chains = U->C;
   return BSS_OK;
 }
@@ -1095,6 +1175,12 @@ bss_status bss_reset_measurements(bss_ctx *c) {
   return BSS_OK;
 }
 
+bss_status bss_synchronize(bss_ctx *c) {
+  bss_status st = usable(c);
+  if (st != BSS_OK) return st;
+  return check_err(c);
+}
+
 bss_status bss_reset_stats(bss_ctx *c) {
   bss_status st = usable(c);
   if (st != BSS_OK) return st;
@@ -1237,6 +1323,7 @@ void bss_destroy(bss_ctx *c) {
     for (auto &p : f.pending) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
   for (auto e : c->pool) hipEventDestroy(e);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->sweep_graph) hipGraphExecDestroy(c->sweep_graph);
   if (c->own_mem && c->mem) hipFree(c->mem);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;

@@ -361,3 +361,75 @@ def test_checkpoint_resume_continues_the_chain():
         for s in range(2):
             assert rel(c.green(0, ch, s), a.green(0, ch, s)) < 1e-12
     assert c.stats()["sweeps"] == 4
+
+
+@pytest.mark.parametrize("precision,m32", [("fp64", 0), ("mixed", 1)])
+def test_graph_replays_match_direct_launches(precision, m32):
+    """A sweep captured into a hipGraph and replayed gives bit for bit what
+    direct launches give: the graph context and a NO_GRAPH twin are swept
+    side by side, with direct-launch sweeps (step_slices), synchronisations
+    and a measured sweep between the replays, and compared after each."""
+    import torch
+    L, U, beta, dtau, C = 6, 2.0, 4.0, 0.5, 4
+    inst = dict(L=L, U=U, t=T, beta=beta, dtau=dtau, seed=BASE_SEED, n_chains=C)
+    print(f"[gpu] graph vs direct: 6x6 {precision} fp32_slices={m32}", flush=True)
+    kw = dict(precision=precision, delay_k=8, n_stab=3, fp32_slices=m32)
+    a = bss.Context([inst], stream=torch.cuda.Stream(), **kw)
+    b = bss.Context([inst], stream=torch.cuda.Stream(), flags=bss.FLAG_NO_GRAPH, **kw)
+    lam = int(round(beta / dtau))
+
+    def same(tag):
+        for c in range(C):
+            assert np.array_equal(a.field(0, c), b.field(0, c)), (tag, c)
+            for s in range(2):
+                assert np.array_equal(a.green(0, c, s), b.green(0, c, s)), (tag, c, s)
+
+    for rep in range(4):
+        a.sweep(1)
+        b.sweep(1)
+        a.synchronize()
+        same(f"replay {rep}")
+        a.step_slices(lam)          # a direct-launch sweep between replays
+        b.step_slices(lam)
+        same(f"direct {rep}")
+    a.sweep(2, measure=True)
+    b.sweep(2, measure=True)
+    same("measured")
+    assert a.stats()["sweep_graph"] == 1 and b.stats()["sweep_graph"] == 0
+    assert a.double_occ() == b.double_occ()
+    ga, gb = a.gtau_k()[0], b.gtau_k()[0]
+    assert np.array_equal(ga, gb)
+
+
+def test_batch_of_uneven_instances():
+    """A heterogeneous batch in one context (the multigrid layout: lattices
+    and slice widths of different sizes, each instance on its own streams):
+    every instance follows the oracle chain keyed by (seed + chain, instance
+    index), and sharding an instance's chains changes nothing."""
+    import torch
+    grid = [(4, 0.5, 8), (6, 0.4, 10), (6, 0.5, 8), (8, 0.4, 10)]   # L, dtau, Lambda at beta = 4
+    insts = [dict(L=L, U=2.0, t=T, beta=4.0, dtau=dt, seed=BASE_SEED, n_chains=3) for L, dt, _ in grid]
+    print("[gpu] batch of 4 uneven instances x 3 chains, fp64 k=4 n_stab=4", flush=True)
+    g = bss.Context(insts, precision="fp64", delay_k=4, n_stab=4, stream=torch.cuda.Stream())
+    g.sweep(2)
+    for j, (L, dt, lam) in enumerate(grid):
+        assert g.params(j)["Lambda"] == lam
+        for c in (0, 2):
+            o = oracle.Chain(L, 2.0, T, 4.0, dt, BASE_SEED, j, c, 4)
+            o.sweep(2)
+            assert np.array_equal(g.field(j, c), o.field()), (j, c)
+            for s in range(2):
+                assert rel(g.green(j, c, s), o.green(s)) < 1e-10, (j, c, s)
+        st = g.stats(j)
+        assert st["sweeps"] == 2 and st["proposals"] == 2 * 3 * lam * L * L
+    os.environ["BSS_SHARDS"] = "3"
+    try:
+        h = bss.Context(insts, precision="fp64", delay_k=4, n_stab=4, stream=torch.cuda.Stream())
+    finally:
+        del os.environ["BSS_SHARDS"]
+    h.sweep(2)
+    for j in range(len(grid)):
+        for c in range(3):
+            assert np.array_equal(h.field(j, c), g.field(j, c)), (j, c)
+            for s in range(2):
+                assert np.array_equal(h.green(j, c, s), g.green(j, c, s)), (j, c, s)
