@@ -88,7 +88,7 @@ typedef enum {
 typedef struct {
   uint32_t struct_size;  /* sizeof(bss_options)                                    */
   int32_t precision;     /* bss_precision                                          */
-  int32_t delay_k;       /* delayed-update rank, 1..64; 0 = automatic              */
+  int32_t delay_k;       /* delayed-update rank, 1..32; 0 = automatic              */
   int32_t n_stab;        /* slices between FP64 recomputations; 0 = automatic      */
   void *stream;          /* hipStream_t to run on; NULL = a library-owned stream   */
   void *workspace;       /* optional device memory for all state (caller-owned)    */
@@ -235,6 +235,33 @@ bss_status bss_load(bss_ctx *c, const void *buf, size_t bytes);
  * receives the number of kernel families. */
 bss_status bss_get_profile(bss_ctx *c, bss_kernel_time *out, int32_t cap, int32_t *n_out);
 bss_status bss_reset_profile(bss_ctx *c);
+
+/* Result of bss_autotune. */
+typedef struct {
+  int32_t precision;     /* BSS_PREC_MIXED if some FP32 slices passed, else FP64  */
+  int32_t delay_k, n_stab, fp32_slices;  /* chosen setting                       */
+  int32_t met_bound;     /* 1 if its measured drift is within the bound; 0 if no
+                            candidate was (the smallest n_stab tried is returned) */
+  int32_t candidates;    /* settings timed                                        */
+  double ms_per_sweep;   /* trial time of the chosen setting (all chains)         */
+  double drift_rel_max;  /* its relative wrap drift over the trial sweeps         */
+} bss_tune_result;
+
+/* Autotuner of the launch parameters of one instance (Sec. 2's BSS-QMC sweep
+ * does not fix them; they change cost, not the exact result): chains are
+ * equilibrated for warmup_sweeps in FP64 at a short block length, then each
+ * candidate (delay_k, n_stab, fp32_slices) is loaded with those fields and
+ * timed over trial_sweeps; the fastest whose relative wrap drift (as in
+ * bss_stats.drift_rel_max) stays <= drift_bound is returned.  The search
+ * takes n_stab in {2, 3, 4, 5, 6, 8, 10, 12, 16, 20} (at most Lambda) at the
+ * automatic delay depth, then delay_k from three depths suited to N, then
+ * (precision MIXED) fp32_slices = 1, 2, ... until the bound fails.  Other
+ * fields of *base (precision, flags other than tracing) are kept.  Allocates
+ * and frees its own trial contexts on the current device; synchronous.
+ * INVALID_ARG: NULL pointers, drift_bound <= 0, warmup_sweeps < 0,
+ * trial_sweeps < 1, or an invalid instance or options. */
+bss_status bss_autotune(const bss_instance *inst, const bss_options *base, double drift_bound,
+                        int32_t warmup_sweeps, int32_t trial_sweeps, bss_tune_result *out);
 
 /* Release the context (NULL is allowed). */
 void bss_destroy(bss_ctx *c);

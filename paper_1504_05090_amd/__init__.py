@@ -25,7 +25,7 @@ EXPORTS = [
     "bss_step_slices", "bss_measure_gtau_k", "bss_measure_double_occ", "bss_reset_measurements", "bss_reset_stats", "bss_synchronize",
     "bss_get_green", "bss_get_field", "bss_set_field", "bss_set_trace", "bss_get_trace",
     "bss_get_stats", "bss_save", "bss_load", "bss_destroy", "bss_status_string", "bss_last_error",
-    "bss_get_profile", "bss_reset_profile",
+    "bss_get_profile", "bss_reset_profile", "bss_autotune",
 ]
 
 
@@ -48,6 +48,12 @@ class Stats(ctypes.Structure):
                 ("Lambda", ctypes.c_int32), ("delay_k", ctypes.c_int32), ("n_stab", ctypes.c_int32),
                 ("fp32_slices", ctypes.c_int32), ("drift_rel_max", ctypes.c_double),
                 ("drift_rel_mean", ctypes.c_double), ("sweep_graph", ctypes.c_int32)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("delay_k", ctypes.c_int32), ("n_stab", ctypes.c_int32),
+                ("fp32_slices", ctypes.c_int32), ("met_bound", ctypes.c_int32), ("candidates", ctypes.c_int32),
+                ("ms_per_sweep", ctypes.c_double), ("drift_rel_max", ctypes.c_double)]
 
 
 class KernelTime(ctypes.Structure):
@@ -95,6 +101,7 @@ def lib():
         L.bss_load.argtypes = [vp, vp, sz]
         L.bss_get_profile.argtypes = [vp, P(KernelTime), i32, P(i32)]
         L.bss_reset_profile.argtypes = [vp]
+        L.bss_autotune.argtypes = [P(Instance), P(Options), dbl, i32, i32, P(TuneResult)]
         L.bss_destroy.argtypes = [vp]
         L.bss_destroy.restype = None
         L.bss_status_string.argtypes = [i32]
@@ -276,3 +283,24 @@ class Context:
     def load(self, data: bytes):
         buf = ctypes.create_string_buffer(data, len(data))
         self._check(lib().bss_load(self._h, buf, len(data)), "bss_load")
+
+
+def autotune(instance: dict, precision="fp64", drift_bound=1e-6, warmup_sweeps=4, trial_sweeps=2, flags=0) -> dict:
+    """Pick delay_k, n_stab and fp32_slices for one instance by timing trial
+    sweeps under a relative wrap-drift bound (bss_autotune)."""
+    import torch  # the trial contexts run on the current device
+
+    if not torch.cuda.is_available():
+        raise BssError(BSS_E_DEVICE, "no GPU visible: the BSS-QMC library runs on gfx950 only")
+    d = instance
+    inst = Instance(int(d["L"]), float(d["U"]), float(d.get("t", 0.25)), float(d["beta"]), float(d["dtau"]),
+                    int(d["seed"]), int(d["n_chains"]))
+    opt = make_options(precision, flags=flags)
+    res = TuneResult()
+    st = lib().bss_autotune(ctypes.byref(inst), ctypes.byref(opt), float(drift_bound), int(warmup_sweeps),
+                            int(trial_sweeps), ctypes.byref(res))
+    if st != BSS_OK:
+        raise BssError(st, f"bss_autotune: {lib().bss_status_string(st).decode()}")
+    out = {f: getattr(res, f) for f, _ in TuneResult._fields_}
+    out["precision"] = "mixed" if res.precision == PREC["mixed"] else "fp64"
+    return out

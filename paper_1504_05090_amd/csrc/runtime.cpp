@@ -1310,6 +1310,159 @@ bss_status bss_reset_profile(bss_ctx *c) {
   return BSS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+struct Trial {
+  int k = 0, ns = 0, m32 = 0;
+  double ms = 0.0, drift = 0.0;
+  bool ok = false;     // ran and stayed within the bound
+};
+
+// one candidate: fresh context, fields from the checkpoint, one untimed sweep
+// (it captures the graph), then trial sweeps timed with events
+bss_status run_trial(const bss_instance &in, bss_options o, const std::vector<char> &ck, int trials, double bound,
+                     Trial &t) {
+  o.delay_k = t.k;
+  o.n_stab = t.ns;
+  o.fp32_slices = t.m32;
+  o.workspace = nullptr;
+  o.workspace_bytes = 0;
+  bss_ctx *c = nullptr;
+  bss_status st = create_impl(&in, 1, &o, &c);
+  if (st != BSS_OK) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = 0.0f;
+  st = bss_load(c, ck.data(), ck.size());
+  if (st == BSS_OK) st = bss_sweep(c, 1, 0);
+  if (st == BSS_OK) st = bss_reset_stats(c);
+  if (st == BSS_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = BSS_E_DEVICE;
+  if (st == BSS_OK && hipEventRecord(e0, c->stream) != hipSuccess) st = BSS_E_DEVICE;
+  if (st == BSS_OK) st = bss_sweep(c, trials, 0);
+  if (st == BSS_OK && hipEventRecord(e1, c->stream) != hipSuccess) st = BSS_E_DEVICE;
+  bss_stats s{};
+  if (st == BSS_OK) st = bss_get_stats(c, 0, &s);   // synchronises
+  if (st == BSS_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BSS_E_DEVICE;
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  bss_destroy(c);
+  t.m32 = s.fp32_slices;
+  if (st == BSS_E_NUMERICAL || st == BSS_E_STATE) {   // the chain broke down: out of bound
+    t.ok = false;
+    t.drift = INFINITY;
+    return BSS_OK;
+  }
+  if (st != BSS_OK) return st;
+  t.ms = ms / trials;
+  t.drift = s.drift_rel_max;
+  t.ok = std::isfinite(t.drift) && t.drift <= bound;
+  return BSS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bss_status bss_autotune(const bss_instance *inst, const bss_options *base, double drift_bound, int32_t warmup_sweeps,
+                        int32_t trial_sweeps, bss_tune_result *out) {
+  if (!inst || !out || !(drift_bound > 0.0) || warmup_sweeps < 0 || trial_sweeps < 1) return BSS_E_INVALID_ARG;
+  std::string why;
+  if (!check_options(base, why)) return BSS_E_INVALID_ARG;
+  bss_options opt;
+  bss_options_default(&opt);
+  if (base) opt = *base;
+  opt.flags &= ~(BSS_FLAG_RECORD_TRACE | BSS_FLAG_REPLAY_TRACE | BSS_FLAG_PROFILE);
+  opt.trace_sweeps = 0;
+  opt.stream = nullptr;
+  bss_status code;
+  if (!valid_instance(*inst, why, code)) return code;
+  const int N = inst->L * inst->L, Lam = (int)std::lround(inst->beta / inst->dtau);
+  std::memset(out, 0, sizeof(*out));
+
+  // equilibrated fields: FP64, short blocks
+  std::vector<char> ck;
+  {
+    bss_options o0 = opt;
+    o0.precision = BSS_PREC_FP64;
+    o0.n_stab = std::min(4, Lam);
+    o0.fp32_slices = 0;
+    o0.workspace = nullptr;
+    o0.workspace_bytes = 0;
+    bss_ctx *c = nullptr;
+    bss_status st = create_impl(inst, 1, &o0, &c);
+    if (st != BSS_OK) return st;
+    size_t n = 0;
+    st = bss_sweep(c, warmup_sweeps, 0);
+    if (st == BSS_OK) st = bss_save(c, nullptr, &n);
+    if (st == BSS_OK) { ck.resize(n); st = bss_save(c, ck.data(), &n); }
+    bss_destroy(c);
+    if (st != BSS_OK) return st;
+  }
+
+  const int k_auto = auto_k(N);
+  auto better = [](const Trial &a, const Trial &b) {   // a beats b
+    if (a.ok != b.ok) return a.ok;
+    if (!a.ok) return a.ns < b.ns;                     // nothing passes: the safest
+    return a.ms < b.ms;
+  };
+  Trial best;
+  bool have = false;
+  int tried = 0;
+  auto consider = [&](Trial t) -> bss_status {
+    const bss_status st = run_trial(*inst, opt, ck, trial_sweeps, drift_bound, t);
+    if (st != BSS_OK) return st;
+    ++tried;
+    if (!have || better(t, best)) { best = t; have = true; }
+    return BSS_OK;
+  };
+  // 1. block length, FP64 slices only
+  const int ns_list[] = {2, 3, 4, 5, 6, 8, 10, 12, 16, 20};
+  const int prec = opt.precision;
+  opt.precision = BSS_PREC_FP64;   // phases 1 and 2 run every slice in FP64
+  for (int ns : ns_list) {
+    if (ns > Lam) break;
+    Trial t;
+    t.k = k_auto; t.ns = ns; t.m32 = 0;
+    const bss_status st = consider(t);
+    if (st != BSS_OK) return st;
+  }
+  // 2. delay depth at that block length
+  const int k_list_small[] = {1, 4, 8}, k_list_mid[] = {4, 8, 16}, k_list_big[] = {8, 16, 32};
+  const int *kl = N <= 16 ? k_list_small : (N <= 64 ? k_list_mid : k_list_big);
+  const int ns_best = best.ns;
+  for (int q = 0; q < 3; ++q) {
+    if (kl[q] == k_auto) continue;
+    Trial t;
+    t.k = kl[q]; t.ns = ns_best; t.m32 = 0;
+    const bss_status st = consider(t);
+    if (st != BSS_OK) return st;
+  }
+  // 3. FP32 slices at the end of each block
+  opt.precision = prec;
+  if (prec == BSS_PREC_MIXED && best.ok) {
+    const int k_best = best.k;
+    for (int m = 1; m <= ns_best; ++m) {
+      Trial t;
+      t.k = k_best; t.ns = ns_best; t.m32 = m;
+      const bss_status st = run_trial(*inst, opt, ck, trial_sweeps, drift_bound, t);
+      if (st != BSS_OK) return st;
+      ++tried;
+      if (!t.ok) break;
+      if (better(t, best)) best = t;
+    }
+  }
+  out->delay_k = best.k;
+  out->n_stab = best.ns;
+  out->fp32_slices = best.m32;
+  out->precision = best.m32 > 0 ? BSS_PREC_MIXED : BSS_PREC_FP64;
+  out->met_bound = best.ok ? 1 : 0;
+  out->candidates = tried;
+  out->ms_per_sweep = best.ms;
+  out->drift_rel_max = best.drift;
+  return BSS_OK;
+}
+
 void bss_destroy(bss_ctx *c) {
   if (!c) return;
   if (c->stream) hipStreamSynchronize(c->stream);

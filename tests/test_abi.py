@@ -93,3 +93,16 @@ def test_create_without_gpu_fails_loudly():
     assert st == bss.BSS_E_DEVICE and not h.value
     with pytest.raises(bss.BssError):
         bss.Context([dict(L=4, U=2.0, beta=4.0, dtau=0.5, seed=1, n_chains=1)])
+
+
+def test_autotune_rejects_invalid_arguments():
+    L = bss.lib()
+    inst = bss.Instance(4, 2.0, 0.25, 4.0, 0.5, 1, 2)
+    res = bss.TuneResult()
+    o = bss.make_options()
+    assert L.bss_autotune(None, ctypes.byref(o), 1e-6, 2, 2, ctypes.byref(res)) == bss.BSS_E_INVALID_ARG
+    assert L.bss_autotune(ctypes.byref(inst), ctypes.byref(o), 0.0, 2, 2, ctypes.byref(res)) == bss.BSS_E_INVALID_ARG
+    assert L.bss_autotune(ctypes.byref(inst), ctypes.byref(o), 1e-6, 2, 0, ctypes.byref(res)) == bss.BSS_E_INVALID_ARG
+    assert L.bss_autotune(ctypes.byref(inst), ctypes.byref(o), 1e-6, 2, 2, None) == bss.BSS_E_INVALID_ARG
+    bad = bss.Instance(5, 2.0, 0.25, 4.0, 0.5, 1, 2)
+    assert L.bss_autotune(ctypes.byref(bad), ctypes.byref(o), 1e-6, 2, 2, ctypes.byref(res)) == bss.BSS_E_UNSUPPORTED

@@ -433,3 +433,28 @@ def test_batch_of_uneven_instances():
             assert np.array_equal(h.field(j, c), g.field(j, c)), (j, c)
             for s in range(2):
                 assert np.array_equal(h.green(j, c, s), g.green(j, c, s)), (j, c, s)
+
+
+def test_autotuner_respects_the_drift_bound():
+    """The tuner's choice meets the bound it was given, and a context built
+    with the chosen delay depth and block length runs the same Markov chain
+    as the oracle (the setting changes cost, not the chain)."""
+    inst = dict(L=6, U=2.0, t=T, beta=8.0, dtau=0.5, seed=BASE_SEED, n_chains=4)
+    print("[gpu] autotune 6x6 beta=8, 4 chains", flush=True)
+    loose = bss.autotune(inst, "mixed", drift_bound=1e-6, warmup_sweeps=3, trial_sweeps=2)
+    tight = bss.autotune(inst, "mixed", drift_bound=1e-11, warmup_sweeps=3, trial_sweeps=2)
+    print(f"[gpu] loose {loose}\n[gpu] tight {tight}")
+    for r in (loose, tight):
+        assert r["candidates"] >= 3
+        assert r["n_stab"] in (2, 3, 4, 5, 6, 8, 10, 12, 16)
+        assert 0 <= r["fp32_slices"] <= r["n_stab"]
+        assert (r["precision"] == "mixed") == (r["fp32_slices"] > 0)
+    assert loose["met_bound"] == 1 and loose["drift_rel_max"] <= 1e-6
+    if tight["met_bound"]:
+        assert tight["drift_rel_max"] <= 1e-11
+    g = bss.Context([inst], precision="fp64", delay_k=loose["delay_k"], n_stab=loose["n_stab"])
+    g.sweep(2)
+    for c in range(2):
+        o = oracle.Chain(6, 2.0, T, 8.0, 0.5, BASE_SEED, 0, c, loose["n_stab"])
+        o.sweep(2)
+        assert np.array_equal(g.field(0, c), o.field())
