@@ -35,6 +35,28 @@ sys.path.insert(0, ROOT)
 METRIC = "HS field updates/sec at 16x16, β=20 (FP32+FP64-stab vs FP64), max|ΔG| vs oracle"
 PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 
+# HBM bytes per launch (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0, the scales a
+# 256 MiB device copy gives) from profiles/sweep_16x16_b20_hbm_traffic.md,
+# valid while the kernel's source file is the one the counters were taken on
+# (sha1 prefix); otherwise the traffic is reported as null.
+TRAFFIC = {
+    "flip_f64": (1.220e9, "k_flip.hip", "ea3f308efb6f"),
+    "flip_f32": (5.775e8, "k_flip.hip", "ea3f308efb6f"),
+    "qr_udv": (2.817e9, "k_qr.hip", "2f24f3565c6e"),
+    "qr_solve": (3.467e9, "k_qr.hip", "2f24f3565c6e"),
+    "wrap_f32": (2.046e8, "k_gemm.hip", "b592526b28ba"),
+}
+
+
+def traffic_of(fam: str):
+    import hashlib
+    if fam not in TRAFFIC:
+        return None
+    val, src, sha = TRAFFIC[fam]
+    path = os.path.join(ROOT, "paper_1504_05090_amd", "csrc", src)
+    with open(path, "rb") as f:
+        return val if hashlib.sha1(f.read()).hexdigest()[:12] == sha else None
+
 
 def family_flops(fam: str, N: int, mats: int, chains: int, acc: float, k: int) -> tuple[float, str]:
     """Algorithmic flops of one launch of a kernel family and its MFMA dtype."""
@@ -73,6 +95,25 @@ def run_path(bss, inst, precision, k, n_stab, steps, warmup, fp32_slices=0, prof
     return ctx, ms, st, prof
 
 
+def run_batch(bss, insts, steps, warmup, flags):
+    """Heterogeneous batch in one context: updates/s over all instances."""
+    import torch
+    stream = torch.cuda.Stream()
+    ctx = bss.Context(insts, precision="fp64", stream=stream, flags=flags)
+    ctx.sweep(warmup)
+    ctx.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ctx.sweep(steps)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    upd = sum(d["n_chains"] * d["L"] ** 2 * int(round(d["beta"] / d["dtau"])) for d in insts)
+    graph = ctx.stats(0)["sweep_graph"]
+    del ctx
+    return upd * steps / (ms / 1e3), ms / steps, graph
+
+
 def summary(st):
     return {"acceptance": st["accepted"] / max(1, st["proposals"]), "drift_rel_max": st["drift_rel_max"],
             "drift_rel_mean": st["drift_rel_mean"], "fp32_slices": st["fp32_slices"]}
@@ -86,6 +127,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-chains", type=int, default=0, help="oracle chains for the CPU baseline (0 = cores)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the multigrid-batch measurement")
+    ap.add_argument("--no-oracle-check", action="store_true", help="skip the sampled comparison with the oracle")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB between two device buffers three times (a plain copy kernel of "
+                         "known size, to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the chains are independent Markov chains and this build has "
@@ -94,6 +140,17 @@ def main():
 
     import paper_1504_05090_amd as bss
     from paper_1504_05090_amd.workloads import BASE_SEED, CONFIGS, T_HOP
+
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 x {args.calibrate_copy} MiB device-to-device", file=sys.stderr, flush=True)
+        del src, dst
 
     cfg = CONFIGS["C4"]
     p = cfg["instances"][0]
@@ -113,6 +170,8 @@ def main():
     # sampled chains against the oracle's G computed from scratch for the GPU's field
     max_dg = None
     try:
+        if args.no_oracle_check:
+            raise RuntimeError("not requested")
         import oracle
         o = oracle.Chain(p["L"], p["U"], T_HOP, p["beta"], p["dtau"], BASE_SEED, 0, 0, n_stab)
         errs = []
@@ -164,12 +223,28 @@ def main():
     peak = PEAK.get(dt)
     roofline = {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12 if achieved else None,
                 "peak": peak / 1e12 if peak else None, "unit": "TFLOP/s",
-                "frac": (achieved / peak) if (achieved and peak) else None, "traffic": None,
+                "frac": (achieved / peak) if (achieved and peak) else None, "traffic": traffic_of(dom),
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "avg_launch_ms": avg_ms, "launches": launches,
                 "mfma_fraction_of_sweep": mfma_time / (msp / 1e3),
                 "breakdown_ms_per_step": {kf: round(v[1] / psteps, 3) for kf, v in fams}}
     print(f"[bench] profile ({msp / psteps:.2f} ms/step): {roofline['breakdown_ms_per_step']}", file=sys.stderr,
           flush=True)
+
+    # the multigrid batch: 16 uneven instances x 32 chains, graph replays
+    # against direct launches
+    batch = None
+    if not args.no_batch:
+        c3 = CONFIGS["C3"]
+        insts = [dict(L=q["L"], U=q["U"], t=T_HOP, beta=q["beta"], dtau=q["dtau"], seed=BASE_SEED,
+                      n_chains=c3["chains"]) for q in c3["instances"]]
+        v_graph, ms_graph, used_graph = run_batch(bss, insts, 5, 3, 0)
+        v_direct, ms_direct, _ = run_batch(bss, insts, 5, 3, bss.FLAG_NO_GRAPH)
+        batch = {"workload": "16 instances L in {6,8,10,12} x dtau in {0.4,0.5,0.625,0.8}, U=2, beta=20, "
+                             "32 chains each, FP64, automatic k and n_stab",
+                 "value": v_graph, "unit": "updates/s", "ms_per_step": ms_graph, "sweep_graph": used_graph,
+                 "direct_launch_value": v_direct, "direct_launch_ms_per_step": ms_direct}
+        print(f"[bench] batch C3: {batch}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -193,7 +268,7 @@ def main():
         "drift_rel_max": mixed["drift_rel_max"], "drift_rel_mean": mixed["drift_rel_mean"],
         "max_dG_vs_oracle_sweep_end": max_dg, "acceptance": mixed["acceptance"],
         "fp64_path": fp64, "speedup_vs_fp64": (value / fp64_value) if fp64_value else None,
-        "all_fp32_bulk": all32,
+        "all_fp32_bulk": all32, "multigrid_batch": batch,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out))
