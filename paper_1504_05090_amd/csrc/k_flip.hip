@@ -93,11 +93,14 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
   extern __shared__ char smem_raw[];
   T *Xs = (T *)smem_raw;                                  // [fb][KM+1]
   T *Ys = Xs + a.fb * (KM + 1);                           // [KM][blockDim+1]
-  __shared__ int first[16];
-  __shared__ T bX[2][KM], bY[2][KM];
-  __shared__ double bF[2];
-  __shared__ double s_logw;
-  __shared__ int s_acc, s_bad;
+  // per-acceptance exchange, double-buffered by the parity of the acceptance
+  // so that one barrier separates consecutive acceptances
+  __shared__ int first[2][16];
+  __shared__ T bX[2][2][KM], bY[2][2][KM];
+  __shared__ double bF[2][2];
+  __shared__ double s_R[MAXT];     // accepted ratios, logged after the loop
+  __shared__ double red[16];
+  __shared__ int s_acc;
 
   const int N = a.N, j = threadIdx.x, lane = j & 63, w = j >> 6, nw = blockDim.x >> 6;
   const int c = blockIdx.x;
@@ -131,10 +134,10 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
   d[0] = own ? (double)G[0][(long)j * N + j] : 0.0;
   d[1] = own ? (double)G[1][(long)j * N + j] : 0.0;
   bool mine = false;   // my site was accepted
-  if (j == 0) { s_logw = 0.0; s_acc = 0; s_bad = 0; }
+  if (j == 0) s_acc = 0;
   __syncthreads();
 
-  int m = 0, pos = 0;
+  int m = 0, pos = 0, par = 0;
   for (;;) {
     bool acc = false;
     if (own && j >= pos) {
@@ -144,29 +147,13 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
       acc = (a.trace_mode == 2) ? forced : (uj < R);
     }
     const unsigned long long bal = __ballot(acc);
-    if (lane == 0) first[w] = bal ? (w * 64 + __ffsll((long long)bal) - 1) : 0x7fffffff;
+    if (lane == 0) first[par][w] = bal ? (w * 64 + __ffsll((long long)bal) - 1) : 0x7fffffff;
     __syncthreads();
     int ist = 0x7fffffff;
-    for (int q = 0; q < nw; ++q) ist = min(ist, first[q]);
+    for (int q = 0; q < nw; ++q) ist = min(ist, first[par][q]);
     if (ist >= N) break;
-    if (j == ist) {
-      const double du = hj > 0 ? a.dlt_up_p : a.dlt_up_m;
-      const double dd = hj > 0 ? a.dlt_dn_p : a.dlt_dn_m;
-      const double Ru = 1.0 + (1.0 - d[0]) * du, Rd = 1.0 + (1.0 - d[1]) * dd;
-      const double R = Ru * Rd;
-      bF[0] = du / Ru;
-      bF[1] = dd / Rd;
-#pragma unroll
-      for (int s = 0; s < KM; ++s) { bX[0][s] = xs[0][s]; bY[0][s] = ys[0][s]; bX[1][s] = xs[1][s]; bY[1][s] = ys[1][s]; }
-      if (!(R > 0.0) || !isfinite(R)) s_bad = 1;
-      s_logw += log(R);
-      s_acc += 1;
-      hj = -hj;
-      hl[j] = (int8_t)hj;
-      mine = true;
-    }
-    __syncthreads();
-    // row ist and column ist of G0 for both spins: four independent loads
+    // row ist and column ist of G0 for both spins: four independent loads,
+    // issued before the accepted site's data is exchanged
     T gr[2] = {(T)0, (T)0}, gc[2] = {(T)0, (T)0};
     if (own) {
 #pragma unroll
@@ -175,15 +162,33 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
         gc[sp] = G[sp][(long)j * N + ist];
       }
     }
+    if (j == ist) {
+      const double du = hj > 0 ? a.dlt_up_p : a.dlt_up_m;
+      const double dd = hj > 0 ? a.dlt_dn_p : a.dlt_dn_m;
+      const double Ru = 1.0 + (1.0 - d[0]) * du, Rd = 1.0 + (1.0 - d[1]) * dd;
+      bF[par][0] = du / Ru;
+      bF[par][1] = dd / Rd;
+#pragma unroll
+      for (int s = 0; s < KM; ++s) {
+        bX[par][0][s] = xs[0][s]; bY[par][0][s] = ys[0][s];
+        bX[par][1][s] = xs[1][s]; bY[par][1][s] = ys[1][s];
+      }
+      s_R[s_acc] = Ru * Rd;
+      s_acc += 1;
+      hj = -hj;
+      hl[j] = (int8_t)hj;
+      mine = true;
+    }
+    __syncthreads();
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp) {
       T cv = gc[sp], rv = gr[sp];
 #pragma unroll
       for (int s = 0; s < KM; ++s) {
-        cv -= xs[sp][s] * bY[sp][s];
-        rv -= bX[sp][s] * ys[sp][s];
+        cv -= xs[sp][s] * bY[par][sp][s];
+        rv -= bX[par][sp][s] * ys[sp][s];
       }
-      const T xn = (T)bF[sp] * ((j == ist ? (T)1 : (T)0) - cv);
+      const T xn = (T)bF[par][sp] * ((j == ist ? (T)1 : (T)0) - cv);
       const T yn = own ? rv : (T)0;
       const T xv = own ? xn : (T)0;
 #pragma unroll
@@ -193,6 +198,10 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
     }
     ++m;
     pos = ist + 1;
+    par ^= 1;
+    // No barrier here: the next acceptance writes the other parity's buffers,
+    // and the one after can only write these once every thread has passed
+    // the next ballot barrier, i.e. finished reading them.
     if (m == a.k) {
       flush_spin<T, KM>(G[0], N, a.fb, xs[0], ys[0], Xs, Ys);
       flush_spin<T, KM>(G[1], N, a.fb, xs[1], ys[1], Xs, Ys);
@@ -202,7 +211,6 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
       d[1] = own ? (double)G[1][(long)j * N + j] : 0.0;
       m = 0;
     }
-    __syncthreads();
   }
   if (m > 0) {
     flush_spin<T, KM>(G[0], N, a.fb, xs[0], ys[0], Xs, Ys);
@@ -219,12 +227,23 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
     if (a.trace_mode == 1 && trace_idx >= 0) a.trace[trace_idx] = mine ? 1 : 0;
   }
   __syncthreads();
+  // log-weight of the slice's accepted ratios (FP64), and the check that
+  // every accepted ratio was positive and finite
+  const int nacc = s_acc;
+  double lg = 0.0, bad = 0.0;
+  for (int q = j; q < nacc; q += blockDim.x) {
+    const double R = s_R[q];
+    if (!(R > 0.0) || !isfinite(R)) bad = 1.0;
+    lg += log(R);
+  }
+  lg = block_sum(lg, red);
+  bad = block_max(bad, red);
   if (j == 0) {
     ChainStats *st = a.stats + c;
     st->proposals += N;
-    st->accepted += s_acc;
-    st->logw += s_logw;
-    if (s_bad) atomicOr(a.err, 1);
+    st->accepted += nacc;
+    st->logw += lg;
+    if (bad > 0.0) atomicOr(a.err, 1);
   }
 }
 
@@ -234,7 +253,7 @@ hipError_t launch_k(const FlipArgs &a0, hipStream_t s) {
   const int threads = ((a.N + 63) / 64) * 64;
   // rows of X staged per flush block: as many as fit next to Y^T in ~150 KB
   const size_t ybytes = sizeof(T) * (size_t)KM * (threads + 1);
-  const size_t budget = 150 * 1024;
+  const size_t budget = 146 * 1024;   // next to ~10 KB of static LDS
   int fb = 16;
   while (fb < a.N && ybytes + sizeof(T) * (size_t)(fb + 16) * (KM + 1) <= budget) fb += 16;
   a.fb = fb;

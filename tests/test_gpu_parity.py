@@ -73,16 +73,20 @@ def test_free_running_sweeps(L, U, beta, dtau, k, n_stab):
     g = ctx(L, U, beta, dtau, 2, k=k, n_stab=n_stab)
     g.sweep(2)
     odrift = 0.0
+    ologw = 0.0
     for c in range(2):
         o = oracle.Chain(L, U, T, beta, dtau, BASE_SEED, 0, c, n_stab)
         o.sweep(2)
         odrift = max(odrift, o.stats()["drift_max"])
+        ologw += o.stats()["logw"]
         assert np.array_equal(g.field(0, c), o.field()), c
         for s in range(2):
             assert rel(g.green(0, c, s), o.green(s)) < 1e-10
     st = g.stats()
     assert st["sweeps"] == 2 and st["proposals"] == 2 * 2 * st["Lambda"] * st["N"]
     assert 0 < st["accepted"] < st["proposals"]
+    # FP64 accumulation of the accepted determinant ratios: sum of log R
+    assert abs(st["logw"] - ologw) <= 1e-9 * st["accepted"], (st["logw"], ologw)
     # the wrap drift of the delayed-update path stays within a small factor of
     # the plain rank-1 reference on the same field history
     print(f"[gpu] drift gpu {st['drift_max']:.3e} oracle {odrift:.3e}")
