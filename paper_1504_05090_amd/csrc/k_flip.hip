@@ -247,6 +247,254 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Paired variant for N <= 256: two lanes per site.  Each lane of the pair
+// keeps every other delayed pair (pair m lives in lane m & 1, slot m >> 1),
+// so the X and Y rows, the dot products of an acceptance and the row that
+// the accepted site publishes are split in half; the halves of a dot product
+// meet through one cross-lane shuffle.  The decision, the diagonal and every
+// value that enters G are the same in both lanes.  Twice the wavefronts also
+// double the loads in flight during a flush.
+
+// G0 <- G0 - X Y^T for one spin with the pairs split over the two lanes of
+// each site (same MFMA scheme as flush_spin).
+template <typename T, int KM>
+__device__ void flush_pairs(T *G, int N, int fb, int ldy, const T (&xs)[KM / 2], const T (&ys)[KM / 2], T *Xs,
+                            T *Ys) {
+  // tiles in flight per wavefront: with twice the wavefronts, 4 FP64 tiles
+  // keep the register budget of 2 waves per SIMD next to the X, Y halves
+  constexpr int H = KM / 2, TB = sizeof(T) == 8 ? 4 : 8;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+  const int j = t >> 1, hf = t & 1;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const bool own = j < N;
+#pragma unroll
+  for (int q = 0; q < H; ++q) Ys[(2 * q + hf) * ldy + j] = own ? ys[q] : (T)0;
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int ctiles = (N + 15) >> 4;
+  for (int i0 = 0; i0 < N; i0 += fb) {
+    __syncthreads();
+    if (j >= i0 && j < i0 + fb) {
+#pragma unroll
+      for (int q = 0; q < H; ++q) Xs[(j - i0) * (KM + 1) + 2 * q + hf] = own ? -xs[q] : (T)0;
+    }
+    __syncthreads();
+    const int nrb = min(fb, N - i0);
+    const int ntiles = ((nrb + 15) >> 4) * ctiles;
+    for (int base = w; base < ntiles; base += nw * TB) {
+      acc_t acc[TB];
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int tile = base + nw * b;
+        const int tr = tile / ctiles, tc = tile % ctiles;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = i0 + tr * 16 + Mfma<T>::row(lane, r), col = tc * 16 + l16;
+          acc[b][r] = (tile < ntiles && row < i0 + nrb && col < N) ? G[(long)row * N + col] : (T)0;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int tile = base + nw * b;
+        if (tile < ntiles) {
+          const int tr = tile / ctiles, tc = tile % ctiles;
+#pragma unroll
+          for (int s0 = 0; s0 < KM; s0 += 4) {
+            const int s = s0 + lq;
+            const T av = Xs[(tr * 16 + l16) * (KM + 1) + s];
+            const T bv = Ys[s * ldy + tc * 16 + l16];
+            acc[b] = Mfma<T>::mac(av, bv, acc[b]);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = i0 + tr * 16 + Mfma<T>::row(lane, r), col = tc * 16 + l16;
+            if (row < i0 + nrb && col < N) G[(long)row * N + col] = acc[b][r];
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int KM>
+__global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
+  static_assert(KM % 8 == 0, "pairs are split over two lanes and staged in steps of 4");
+  constexpr int H = KM / 2;
+  extern __shared__ char smem_raw[];
+  T *Xs = (T *)smem_raw;                                  // [fb][KM+1]
+  T *Ys = Xs + a.fb * (KM + 1);                           // [KM][ldy]
+  __shared__ int first[2][8];
+  __shared__ T bX[2][2][KM], bY[2][2][KM];
+  __shared__ double bF[2][2];
+  __shared__ double s_R[256];
+  __shared__ double red[16];
+  __shared__ int s_acc;
+
+  const int N = a.N, t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
+  const int j = t >> 1, hf = t & 1;
+  const int ldy = (blockDim.x >> 1) + 1;
+  const int c = blockIdx.x;
+  const bool own = j < N;
+  const long NN = (long)N * N;
+  T *G[2] = {(T *)a.G + (2L * c) * NN, (T *)a.G + (2L * c + 1) * NN};
+  int8_t *hl = a.h + ((long)c * a.Lam + (a.l - 1)) * N;
+  const int64_t sweep = *a.sweep;
+
+  int hj = own ? hl[j] : 1;
+  double uj = 2.0;
+  bool forced = false;
+  long trace_idx = -1;
+  if (own && a.trace_mode != 0) {
+    const int64_t rel = sweep - *a.trace_base;
+    if (rel >= 0 && rel < a.trace_sweeps)
+      trace_idx = ((rel * a.chains_total + a.chain0 + c) * (long)a.Lam + (a.l - 1)) * N + j;
+  }
+  if (own) {
+    if (a.trace_mode == 2) {
+      if (trace_idx >= 0) forced = a.trace[trace_idx] != 0;
+      else if (hf == 0) atomicOr(a.err, 8);   // replay past the supplied history
+    } else {
+      uj = uniform53(philox_word0((uint64_t)sweep, (uint64_t)(a.l - 1) * N + j, 0, 0, a.seed + (uint64_t)(a.chain0 + c), a.inst));
+    }
+  }
+  T xs[2][H], ys[2][H];
+#pragma unroll
+  for (int q = 0; q < H; ++q) { xs[0][q] = xs[1][q] = ys[0][q] = ys[1][q] = (T)0; }
+  double d[2];
+  d[0] = own ? (double)G[0][(long)j * N + j] : 0.0;
+  d[1] = own ? (double)G[1][(long)j * N + j] : 0.0;
+  bool mine = false;
+  if (t == 0) s_acc = 0;
+  __syncthreads();
+
+  int m = 0, pos = 0, par = 0;
+  for (;;) {
+    bool acc = false;
+    if (own && j >= pos) {
+      const double du = hj > 0 ? a.dlt_up_p : a.dlt_up_m;
+      const double dd = hj > 0 ? a.dlt_dn_p : a.dlt_dn_m;
+      const double R = (1.0 + (1.0 - d[0]) * du) * (1.0 + (1.0 - d[1]) * dd);
+      acc = (a.trace_mode == 2) ? forced : (uj < R);
+    }
+    // both lanes of a site decide alike: look at the even lanes
+    const unsigned long long bal = __ballot(acc) & 0x5555555555555555ull;
+    if (lane == 0) first[par][w] = bal ? (w * 32 + ((__ffsll((long long)bal) - 1) >> 1)) : 0x7fffffff;
+    __syncthreads();
+    int ist = 0x7fffffff;
+    for (int q = 0; q < nw; ++q) ist = min(ist, first[par][q]);
+    if (ist >= N) break;
+    T gr[2] = {(T)0, (T)0}, gc[2] = {(T)0, (T)0};
+    if (own) {
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp) {
+        gr[sp] = G[sp][(long)ist * N + j];
+        gc[sp] = G[sp][(long)j * N + ist];
+      }
+    }
+    if (j == ist) {
+      const double du = hj > 0 ? a.dlt_up_p : a.dlt_up_m;
+      const double dd = hj > 0 ? a.dlt_dn_p : a.dlt_dn_m;
+      const double Ru = 1.0 + (1.0 - d[0]) * du, Rd = 1.0 + (1.0 - d[1]) * dd;
+#pragma unroll
+      for (int q = 0; q < H; ++q) {
+        bX[par][0][hf * H + q] = xs[0][q]; bY[par][0][hf * H + q] = ys[0][q];
+        bX[par][1][hf * H + q] = xs[1][q]; bY[par][1][hf * H + q] = ys[1][q];
+      }
+      if (hf == 0) {
+        bF[par][0] = du / Ru;
+        bF[par][1] = dd / Rd;
+        s_R[s_acc] = Ru * Rd;
+        s_acc += 1;
+        hl[j] = (int8_t)(-hj);
+      }
+      hj = -hj;
+      mine = true;
+    }
+    __syncthreads();
+    const int slot = m >> 1, mine_half = m & 1;
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      T pc = (T)0, pr = (T)0;
+#pragma unroll
+      for (int q = 0; q < H; ++q) {
+        pc += xs[sp][q] * bY[par][sp][hf * H + q];
+        pr += bX[par][sp][hf * H + q] * ys[sp][q];
+      }
+      pc += __shfl_xor(pc, 1, 64);
+      pr += __shfl_xor(pr, 1, 64);
+      const T cv = gc[sp] - pc, rv = gr[sp] - pr;
+      const T xn = own ? (T)bF[par][sp] * ((j == ist ? (T)1 : (T)0) - cv) : (T)0;
+      const T yn = own ? rv : (T)0;
+      if (hf == mine_half) {
+#pragma unroll
+        for (int q = 0; q < H; ++q)
+          if (q == slot) { xs[sp][q] = xn; ys[sp][q] = yn; }
+      }
+      d[sp] -= (double)xn * (double)yn;
+    }
+    ++m;
+    pos = ist + 1;
+    par ^= 1;
+    // no barrier: the next acceptance uses the other parity's buffers (see k_flip)
+    if (m == a.k) {
+      flush_pairs<T, KM>(G[0], N, a.fb, ldy, xs[0], ys[0], Xs, Ys);
+      flush_pairs<T, KM>(G[1], N, a.fb, ldy, xs[1], ys[1], Xs, Ys);
+#pragma unroll
+      for (int q = 0; q < H; ++q) { xs[0][q] = xs[1][q] = ys[0][q] = ys[1][q] = (T)0; }
+      d[0] = own ? (double)G[0][(long)j * N + j] : 0.0;
+      d[1] = own ? (double)G[1][(long)j * N + j] : 0.0;
+      m = 0;
+    }
+  }
+  if (m > 0) {
+    flush_pairs<T, KM>(G[0], N, a.fb, ldy, xs[0], ys[0], Xs, Ys);
+    flush_pairs<T, KM>(G[1], N, a.fb, ldy, xs[1], ys[1], Xs, Ys);
+  }
+  if (own && hf == 0) {
+    T *dv0 = (T *)a.dv + (2L * c) * 2 * N;
+    T *dv1 = dv0 + 2 * N;
+    const T up = hj > 0 ? (T)a.elam : (T)a.emlam;
+    const T dn = hj > 0 ? (T)a.emlam : (T)a.elam;
+    dv0[j] = up; dv0[N + j] = dn;
+    dv1[j] = dn; dv1[N + j] = up;
+    if (a.trace_mode == 1 && trace_idx >= 0) a.trace[trace_idx] = mine ? 1 : 0;
+  }
+  __syncthreads();
+  const int nacc = s_acc;
+  double lg = 0.0, bad = 0.0;
+  for (int q = t; q < nacc; q += blockDim.x) {
+    const double R = s_R[q];
+    if (!(R > 0.0) || !isfinite(R)) bad = 1.0;
+    lg += log(R);
+  }
+  lg = block_sum(lg, red);
+  bad = block_max(bad, red);
+  if (t == 0) {
+    ChainStats *st = a.stats + c;
+    st->proposals += N;
+    st->accepted += nacc;
+    st->logw += lg;
+    if (bad > 0.0) atomicOr(a.err, 1);
+  }
+}
+
+template <typename T, int KM>
+hipError_t launch_pairs(const FlipArgs &a0, hipStream_t s) {
+  FlipArgs a = a0;
+  const int sites = ((a.N + 31) / 32) * 32;           // 32 sites per wavefront
+  const int threads = 2 * sites;
+  const size_t ybytes = sizeof(T) * (size_t)KM * (sites + 1);
+  const size_t budget = 146 * 1024;
+  int fb = 16;
+  while (fb < a.N && ybytes + sizeof(T) * (size_t)(fb + 16) * (KM + 1) <= budget) fb += 16;
+  a.fb = fb;
+  const size_t lds = sizeof(T) * (size_t)fb * (KM + 1) + ybytes;
+  if (threads > 512) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_flip_pairs<T, KM>), dim3(a.chains), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
 template <typename T, int KM>
 hipError_t launch_k(const FlipArgs &a0, hipStream_t s) {
   FlipArgs a = a0;
@@ -270,6 +518,12 @@ hipError_t launch_k(const FlipArgs &a0, hipStream_t s) {
 template <typename T>
 hipError_t launch_t(const FlipArgs &a, hipStream_t s) {
   if (a.k <= 1) return launch_k<T, 1>(a, s);
+  if (a.N <= 256) {   // two lanes per site
+    if (a.k <= 8) return launch_pairs<T, 8>(a, s);
+    if (a.k <= 16) return launch_pairs<T, 16>(a, s);
+    if (a.k <= 32) return launch_pairs<T, 32>(a, s);
+    return hipErrorInvalidValue;
+  }
   if (a.k <= 8) return launch_k<T, 8>(a, s);
   if (a.k <= 16) return launch_k<T, 16>(a, s);
   if (a.k <= 32) return launch_k<T, 32>(a, s);
