@@ -179,9 +179,10 @@ GOLDEN_L16 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", 
 # Stated bound of mixed precision (relative to max(1, max|G|)) on the headline
 # lattice from an equilibrated field: FP32 in the last fp32_slices = 2 slices
 # of every block (the automatic choice at U = 2, dtau = 0.5).  Measured over
-# 128 equilibrated chains x 6 sweeps: relative wrap drift at most 9.5e-5
-# (mean 5.4e-6); the FP64 path's own is 2.9e-5 at n_stab = 8.  Stated: 4x.
-MIXED_BOUND = 4e-4
+# 128 chains: relative wrap drift at most 1.2e-4 (6 sweeps after a 30-sweep
+# FP64 equilibration, mean 5.8e-6) and 3.0e-4 (10 sweeps after 10 mixed
+# warm-up sweeps); the FP64 path's own is 2.9e-5 at n_stab = 8.  Stated: 1e-3.
+MIXED_BOUND = 1e-3
 
 
 @pytest.mark.parametrize("precision,n_stab,m32", [("fp64", 4, 0), ("fp64", 8, 0), ("mixed", 8, 0), ("mixed", 8, 1),
