@@ -7,9 +7,9 @@
 // streams (main, aux).  A sweep issues the shards' launch sequences slice by
 // slice in turn, so the instances of a batch run concurrently and small
 // instances fill the CUs that a large one leaves idle during its
-// latency-bound flip phase.  The left-stack rebuild at the end of a sweep
-// depends only on that sweep's block products: it runs on the aux stream, and
-// the next sweep waits for it only at its first recomputation.  Every
+// latency-bound flip phase.  The left-stack rebuild from a sweep's block
+// products runs on the aux stream at the start of the next sweep, under its
+// first block of slices, which waits for it only at its first recomputation.  Every
 // enqueuing call forks from the context stream and joins back into it, so the
 // caller sees a single asynchronous stream.  Sharding changes no result:
 // random numbers and the accept history are keyed by the chain's index in its
@@ -79,6 +79,7 @@ struct Shard {
   hipStream_t s = nullptr, aux = nullptr;
   hipEvent_t ev_main = nullptr, ev_left = nullptr;
   bool left_pending = false;             // a left rebuild on aux not yet waited for by s
+  bool left_stale = false;               // the left factors predate the block products
   bool cur64 = true;                     // G64 (true) or G32 holds the current G
   int slice = 1;
   int64_t sweeps = 0;
@@ -129,8 +130,8 @@ struct bss_ctx {
   };
   std::vector<Fam> fam;
   std::vector<hipEvent_t> pool;
-  // one captured (unmeasured) sweep, replayed by bss_sweep
-  hipGraphExec_t sweep_graph = nullptr;
+  // one captured (unmeasured) sweep in two parts, replayed by bss_sweep
+  hipGraphExec_t sweep_graph[2] = {nullptr, nullptr};
   bool graphs = false;   // capture and replay sweeps (off: NO_GRAPH, PROFILE, or capture failed)
 };
 
@@ -485,6 +486,7 @@ struct Exec {
     fresh(I.nb - 1, false, I.Gf);
     replace(I.slice, false, 0.0);
     left_rebuild();
+    I.left_stale = false;
   }
 
   void flip(int l) {
@@ -538,14 +540,18 @@ struct Exec {
   }
 
   void slice(int l) {
+    if (l == 1) begin_sweep();
     flip(l);
     wrap();
     if (l % I.n_stab == 0 || l == I.Lam) stabilise(l);
   }
 
-  // sweep counter on the main stream, left rebuild on the aux stream
-  void end_of_sweep() {
-    chk(bump_counter(I.sweep_ctr, I.s));
+  // The left factors of a sweep are rebuilt from the block products of the
+  // sweep before it.  That rebuild runs on the aux stream at the start of the
+  // sweep, under the slices of the first block, which touch neither the
+  // block products nor the QR scratch; the first recomputation waits for it.
+  void begin_sweep() {
+    if (!I.left_stale) return;
     chk(hipEventRecord(I.ev_main, I.s));
     chk(hipStreamWaitEvent(I.aux, I.ev_main, 0));
     s = I.aux;
@@ -553,12 +559,24 @@ struct Exec {
     s = I.s;
     chk(hipEventRecord(I.ev_left, I.aux));
     I.left_pending = true;
+    I.left_stale = false;
+  }
+
+  // sweep counter; the left factors are now due for a rebuild
+  void end_of_sweep() {
+    chk(bump_counter(I.sweep_ctr, I.s));
+    I.left_stale = true;
   }
 
   // measurement of the sweep just finished: Gf holds G(0) = G(1) fresh, the
-  // right chain after each block and the rebuilt left factors are current.
+  // right chain after each block is current, the left factors are rebuilt
+  // here if the next sweep has not done so.
   void measure() {
     wait_left();
+    if (I.left_stale) {
+      left_rebuild();
+      I.left_stale = false;
+    }
     chk(meas_begin(I.ms, I.C, s));
     chk(meas_docc(I.ms, I.Gf, I.C, I.N, s));
     chk(hipMemcpyAsync(I.Gt, I.Gf, sizeof(double) * I.mats * NN(), hipMemcpyDeviceToDevice, s));
@@ -772,43 +790,94 @@ bss_status enqueue_sweeps(bss_ctx *c, int n_sweeps, bool measure) {
   return BSS_OK;
 }
 
-// Capture one unmeasured sweep into an executable graph.  The capture starts
-// from the context stream with nothing pending on the shard streams: launches
-// of the graph are ordered on that stream, so each replay begins after the
-// previous one (left rebuild included) has finished.  Returns false if the
-// runtime refuses the capture; the caller then stays with direct launches.
-// Measured sweeps are not captured: capturing one crashed the host process
-// inside the HIP runtime, so they always launch directly.
-bool capture_sweep(bss_ctx *c) {
-  std::vector<bool> pend(c->sh.size());
-  std::vector<bool> cur(c->sh.size());
-  for (size_t i = 0; i < c->sh.size(); ++i) {
-    pend[i] = c->sh[i].left_pending;
-    cur[i] = c->sh[i].cur64;
-    c->sh[i].left_pending = false;
-  }
+// Enqueue slices [l_from, l_to] of one sweep for every shard (l_from = 1
+// starts the sweep: the left rebuild is launched first, on the aux streams),
+// between a fork from and a join into the context stream.
+bss_status enqueue_range(bss_ctx *c, int l_from, int l_to) {
+  HIP_TRY(c, fork(c));
+  std::vector<Exec> xs;
+  xs.reserve(c->sh.size());
+  for (auto &I : c->sh) xs.emplace_back(c, I);
+  if (l_from == 1)
+    for (auto &x : xs) x.begin_sweep();
+  for (int l = l_from; l <= l_to; ++l)
+    for (auto &x : xs) {
+      if (l > x.I.Lam) continue;
+      x.slice(l);
+      if (l == x.I.Lam) x.end_of_sweep();
+    }
+  for (auto &x : xs)
+    if (x.e != hipSuccess) return exec_failed(c, x);
+  HIP_TRY(c, join(c));
+  return BSS_OK;
+}
+
+bool capture_range(bss_ctx *c, int l_from, int l_to, hipGraphExec_t *out) {
+  *out = nullptr;
   hipGraph_t g = nullptr;
   bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
-    const bss_status st = enqueue_sweeps(c, 1, false);
+    const bss_status st = enqueue_range(c, l_from, l_to);
     const hipError_t e = hipStreamEndCapture(c->stream, &g);
     ok = st == BSS_OK && e == hipSuccess && g != nullptr;
   }
   hipGraphExec_t ex = nullptr;
   if (ok) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
   if (g) hipGraphDestroy(g);
+  if (!ok && ex) {
+    hipGraphExecDestroy(ex);
+    ex = nullptr;
+  }
+  *out = ex;
+  return ok;
+}
+
+// Capture one unmeasured sweep into two executable graphs, both starting
+// from and ending on the context stream: the first holds the left rebuild of
+// the sweep before (aux streams) beside the slices up to the first
+// recomputation, the second the rest of the sweep.  Every cross-stream
+// dependency inside a capture is thus a fork from a stream already in it, or
+// a join into the context stream; a shard stream never waits on its aux
+// stream inside a capture.  Two captures with such a wait (the measured
+// sweep, and the rebuild joined into the first recomputation) each crashed
+// the host process inside the HIP runtime, and the cause could not be shown,
+// so that form is not captured.  Measured sweeps always launch directly.
+// Returns false if the runtime refuses a capture; the caller then stays with
+// direct launches.
+bool capture_sweep(bss_ctx *c) {
+  const size_t n = c->sh.size();
+  std::vector<bool> pend(n), cur(n), stale(n);
+  int l_first = 1 << 30, lam_max = 0;
+  for (size_t i = 0; i < n; ++i) {
+    Shard &I = c->sh[i];
+    pend[i] = I.left_pending;
+    cur[i] = I.cur64;
+    stale[i] = I.left_stale;
+    I.left_pending = false;
+    I.left_stale = true;   // every replay starts with the rebuild of the sweep before
+    l_first = std::min(l_first, std::min(I.n_stab, I.Lam));
+    lam_max = std::max(lam_max, I.Lam);
+  }
+  hipGraphExec_t ga = nullptr, gb = nullptr;
+  bool ok = capture_range(c, 1, l_first - 1, &ga);
+  // the first part's join has ordered the context stream after the rebuilds
+  for (auto &I : c->sh) I.left_pending = false;
+  if (ok) ok = capture_range(c, l_first, lam_max, &gb);
   // a capture enqueues nothing: restore the host-side state it advanced
-  for (size_t i = 0; i < c->sh.size(); ++i) {
+  for (size_t i = 0; i < n; ++i) {
     c->sh[i].left_pending = pend[i];
     c->sh[i].cur64 = cur[i];
+    c->sh[i].left_stale = stale[i];
   }
   c->poisoned = false;
   (void)hipGetLastError();
   if (!ok) {
-    if (ex) hipGraphExecDestroy(ex);
+    if (ga) hipGraphExecDestroy(ga);
+    if (gb) hipGraphExecDestroy(gb);
     return false;
   }
-  c->sweep_graph = ex;
+  c->sweep_graph[0] = ga;
+  c->sweep_graph[1] = gb;
   return true;
 }
 
@@ -824,14 +893,18 @@ bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure) {
     if (I.slice != 1) return fail(c, BSS_E_STATE, "an instance is part-way through a sweep");
   if (n_sweeps == 0) return BSS_OK;
   const bool replay = c->graphs && !measure;
-  if (replay && !c->sweep_graph && !capture_sweep(c)) c->graphs = false;
+  if (replay && !c->sweep_graph[0] && !capture_sweep(c)) c->graphs = false;
   if (replay && c->graphs) {
-    for (int sw = 0; sw < n_sweeps; ++sw) HIP_TRY(c, hipGraphLaunch(c->sweep_graph, c->stream));
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+      HIP_TRY(c, hipGraphLaunch(c->sweep_graph[0], c->stream));
+      HIP_TRY(c, hipGraphLaunch(c->sweep_graph[1], c->stream));
+    }
     // the replays leave what direct launches would: slice 1 in its
     // precision, every left rebuild waited for on the context stream
     for (auto &I : c->sh) {
       I.cur64 = !fp32_slice(I, 1);
       I.left_pending = false;
+      I.left_stale = true;
     }
   } else if ((st = enqueue_sweeps(c, n_sweeps, measure != 0)) != BSS_OK) {
     return st;
@@ -958,10 +1031,11 @@ bss_status bss_set_trace(bss_ctx *c, int32_t inst, const uint8_t *accept, int32_
   HIP_TRY(c, hipMemcpy(U->trace_base, &base, sizeof(base), hipMemcpyHostToDevice));
   U->trace_cap = n_sweeps;   // sweeping past this window is an error
   // the flip launches carry the window length: captured sweeps are stale
-  if (c->sweep_graph) {
-    hipGraphExecDestroy(c->sweep_graph);
-    c->sweep_graph = nullptr;
-  }
+  for (auto &g : c->sweep_graph)
+    if (g) {
+      hipGraphExecDestroy(g);
+      g = nullptr;
+    }
   return BSS_OK;
 }
 
@@ -1007,7 +1081,7 @@ bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
   }
   out->drift_mean = dcnt ? dsum / dcnt : 0.0;
   out->drift_rel_mean = dcnt ? rsum / dcnt : 0.0;
-  out->sweep_graph = c->sweep_graph ? 1 : 0;
+  out->sweep_graph = c->sweep_graph[0] ? 1 : 0;
   out->n_chains = U->C;
   return BSS_OK;
 }
@@ -1476,7 +1550,8 @@ void bss_destroy(bss_ctx *c) {
     for (auto &p : f.pending) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
   for (auto e : c->pool) hipEventDestroy(e);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
-  if (c->sweep_graph) hipGraphExecDestroy(c->sweep_graph);
+  for (auto g : c->sweep_graph)
+    if (g) hipGraphExecDestroy(g);
   if (c->own_mem && c->mem) hipFree(c->mem);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;
