@@ -40,11 +40,12 @@ PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 # valid while the kernel's source file is the one the counters were taken on
 # (sha1 prefix); otherwise the traffic is reported as null.
 TRAFFIC = {
-    "flip_f64": (1.220e9, "k_flip.hip", "ea3f308efb6f"),
-    "flip_f32": (5.775e8, "k_flip.hip", "ea3f308efb6f"),
-    "qr_udv": (2.817e9, "k_qr.hip", "2f24f3565c6e"),
+    "flip_f64": (1.218e9, "k_flip.hip", "7e46c103ee76"),
+    "flip_f32": (5.759e8, "k_flip.hip", "7e46c103ee76"),
+    "qr_udv": (2.816e9, "k_qr.hip", "2f24f3565c6e"),
     "qr_solve": (3.467e9, "k_qr.hip", "2f24f3565c6e"),
     "wrap_f32": (2.046e8, "k_gemm.hip", "b592526b28ba"),
+    "wrap_f64": (5.464e8, "k_gemm.hip", "b592526b28ba"),
 }
 
 
