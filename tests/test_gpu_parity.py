@@ -463,3 +463,18 @@ def test_autotuner_respects_the_drift_bound():
         o = oracle.Chain(6, 2.0, T, 8.0, 0.5, BASE_SEED, 0, c, loose["n_stab"])
         o.sweep(2)
         assert np.array_equal(g.field(0, c), o.field())
+
+
+@pytest.mark.parametrize("L,k,n_stab", [(18, 32, 2), (20, 16, 4)])
+def test_lattices_above_256_sites(L, k, n_stab):
+    """N = 324 and 400: the one-lane-per-site flip kernel (N > 256) and the
+    narrow-panel QR follow the oracle chain: fields bit for bit, G to 1e-10."""
+    beta, dtau = 2.0, 0.5
+    g = ctx(L, 2.0, beta, dtau, 2, k=k, n_stab=n_stab)
+    g.sweep(1)
+    for c in range(2):
+        o = oracle.Chain(L, 2.0, T, beta, dtau, BASE_SEED, 0, c, n_stab)
+        o.sweep(1)
+        assert np.array_equal(g.field(0, c), o.field()), c
+        for s in range(2):
+            assert rel(g.green(0, c, s), o.green(s)) < 1e-10, (c, s)
