@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "HS field updates/sec at 16x16, β=20 (FP32+FP64-stab vs FP64), max|ΔG| vs oracle"
 PEAK = {"f32": 157.3e12, "f64": 78.6e12}
+HBM_PEAK = 8.0e12
 
 # HBM bytes per launch (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0, the scales a
 # 256 MiB device copy gives) from profiles/sweep_16x16_b20_hbm_traffic.md,
@@ -42,10 +43,12 @@ PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 TRAFFIC = {
     "flip_f64": (1.218e9, "k_flip.hip", "7e46c103ee76"),
     "flip_f32": (5.759e8, "k_flip.hip", "7e46c103ee76"),
-    "qr_udv": (2.816e9, "k_qr.hip", "2f24f3565c6e"),
-    "qr_solve": (3.467e9, "k_qr.hip", "2f24f3565c6e"),
-    "wrap_f32": (2.046e8, "k_gemm.hip", "b592526b28ba"),
-    "wrap_f64": (5.464e8, "k_gemm.hip", "b592526b28ba"),
+    "qr_udv": (2.814e9, "k_qr.hip", "2f24f3565c6e"),
+    "qr_solve": (3.468e9, "k_qr.hip", "2f24f3565c6e"),
+    # wraps: one right and one left Kronecker-factor product each (mean of the two)
+    "wrap_f64": (2.726e8, "k_hop.hip", "990a600b01dc"),
+    "wrap_f32": (1.358e8, "k_hop.hip", "990a600b01dc"),
+    "hop_f64": (2.711e8, "k_hop.hip", "990a600b01dc"),
 }
 
 
@@ -59,19 +62,37 @@ def traffic_of(fam: str):
         return val if hashlib.sha1(f.read()).hexdigest()[:12] == sha else None
 
 
-def family_flops(fam: str, N: int, mats: int, chains: int, acc: float, k: int) -> tuple[float, str]:
-    """Algorithmic flops of one launch of a kernel family and its MFMA dtype."""
-    if fam in ("wrap_f32", "wrap_f64", "gemm_f64"):
-        return 2.0 * N ** 3 * mats, fam[-3:]          # one batched N x N x N product
+def family_model(fam: str, N: int, mats: int, chains: int, acc: float, k: int):
+    """Algorithmic work of one launch of a kernel family: (amount, peak per second, bound).
+
+    MFMA-bound families count flops against the dense MFMA peak of their
+    dtype; the Kronecker-factor products (wraps, block and measurement
+    products) count the bytes they must move, X read and Y written once, against
+    HBM bandwidth."""
+    if fam in ("wrap_f32", "wrap_f64", "hop_f64"):
+        esz = 4 if fam.endswith("f32") else 8
+        return 2.0 * mats * N * N * esz, HBM_PEAK, "hbm"
+    if fam == "gemm_f64":
+        return 2.0 * N ** 3 * mats, PEAK["f64"], "mfma"        # one batched N x N x N product
     if fam == "qr_udv":
-        return (8.0 / 3.0) * N ** 3 * mats, "f64"     # Householder R (4/3 N^3) + explicit Q (4/3 N^3)
+        return (8.0 / 3.0) * N ** 3 * mats, PEAK["f64"], "mfma"   # Householder R (4/3 N^3) + explicit Q (4/3 N^3)
     if fam == "qr_solve":
-        return (13.0 / 3.0) * N ** 3 * mats, "f64"    # R (4/3), Q^T on N columns (2), back substitution (1)
+        return (13.0 / 3.0) * N ** 3 * mats, PEAK["f64"], "mfma"  # R (4/3), Q^T on N columns (2), back substitution (1)
     if fam in ("flip_f32", "flip_f64"):
         # per chain and slice, both spins: rank-k flushes 4 a N^3, row/column
         # corrections 4 a N^2 k (a = acceptance)
-        return chains * (4.0 * acc * N ** 3 + 4.0 * acc * N ** 2 * k), fam[-3:]
-    return 0.0, ""
+        return chains * (4.0 * acc * N ** 3 + 4.0 * acc * N ** 2 * k), PEAK[fam[-3:]], "mfma"
+    return 0.0, None, None
+
+
+def _family_roofline(fam, entry, N, mats, chains, acc, k):
+    launches, tot = entry
+    amount, peak, bound = family_model(fam, N, mats, chains, acc, k)
+    if not amount or not launches:
+        return {"launches": launches, "avg_launch_ms": tot / max(1, launches)}
+    avg_ms = tot / launches
+    return {"launches": launches, "avg_launch_ms": round(avg_ms, 5), "bound": bound,
+            "frac": round(amount / (avg_ms / 1e3) / peak, 4)}
 
 
 def run_path(bss, inst, precision, k, n_stab, steps, warmup, fp32_slices=0, profile=False):
@@ -212,23 +233,24 @@ def main():
     acc = stp["accepted"] / max(1, stp["proposals"])
     mats = 2 * C
     fams = sorted(prof.items(), key=lambda kv: -kv[1][1])
-    mfma_time = 0.0
+    bound_time = 0.0
     for fam, (launches, tot) in fams:
-        fl, dt = family_flops(fam, N, mats, C, acc, k)
-        if fl:
-            mfma_time += fl * launches / PEAK[dt]
+        amount, pk, _ = family_model(fam, N, mats, C, acc, k)
+        if amount:
+            bound_time += amount * launches / pk
     dom, (launches, tot) = fams[0]
     avg_ms = tot / max(1, launches)
-    flops, dt = family_flops(dom, N, mats, C, acc, k)
-    achieved = flops / (avg_ms / 1e3) if flops else None
-    peak = PEAK.get(dt)
-    roofline = {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12 if achieved else None,
-                "peak": peak / 1e12 if peak else None, "unit": "TFLOP/s",
+    amount, peak, bound = family_model(dom, N, mats, C, acc, k)
+    achieved = amount / (avg_ms / 1e3) if amount else None
+    scale = 1e9 if bound == "hbm" else 1e12
+    roofline = {"kernel": dom, "bound": bound, "achieved": achieved / scale if achieved else None,
+                "peak": peak / scale if peak else None, "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
                 "frac": (achieved / peak) if (achieved and peak) else None, "traffic": traffic_of(dom),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "avg_launch_ms": avg_ms, "launches": launches,
-                "mfma_fraction_of_sweep": mfma_time / (msp / 1e3),
-                "breakdown_ms_per_step": {kf: round(v[1] / psteps, 3) for kf, v in fams}}
+                "bound_time_fraction_of_sweep": bound_time / (msp / 1e3),
+                "breakdown_ms_per_step": {kf: round(v[1] / psteps, 3) for kf, v in fams},
+                "families": {kf: _family_roofline(kf, v, N, mats, C, acc, k) for kf, v in fams}}
     print(f"[bench] profile ({msp / psteps:.2f} ms/step): {roofline['breakdown_ms_per_step']}", file=sys.stderr,
           flush=True)
 

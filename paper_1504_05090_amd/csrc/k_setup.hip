@@ -41,19 +41,24 @@ __device__ double ring_propagator(int d, int L, double x, bool alternate) {
   return sum;
 }
 
-template <typename T>
-__global__ void k_build_exp(int L, double t, double dtau, double *Em, double *Ep, T *Etm, T *Etp) {
+__global__ void k_build_exp(int L, double t, double dtau, double *Em) {
   const int N = L * L;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)N * N) return;
   const int i = (int)(e / N), j = (int)(e % N);
   const int dx = ((i % L) - (j % L) + L) % L, dy = ((i / L) - (j / L) + L) % L;
   const double x = 2.0 * dtau * t;
-  const double sm = ring_propagator(dx, L, x, false) * ring_propagator(dy, L, x, false);
-  const double sp = ring_propagator(dx, L, x, true) * ring_propagator(dy, L, x, true);
-  Em[e] = sm;
-  Ep[e] = sp;
-  if (Etm) { Etm[e] = (T)sm; Etp[e] = (T)sp; }
+  Em[e] = ring_propagator(dx, L, x, false) * ring_propagator(dy, L, x, false);
+}
+
+__global__ void k_build_ring(int L, double t, double dtau, double *rm, double *rp, float *rtm, float *rtp) {
+  const int d = threadIdx.x;
+  if (d >= L) return;
+  const double x = 2.0 * dtau * t;
+  const double m = ring_propagator(d, L, x, false), p = ring_propagator(d, L, x, true);
+  rm[d] = m;
+  rp[d] = p;
+  if (rtm) { rtm[d] = (float)m; rtp[d] = (float)p; }
 }
 
 // h[c][l][i] = +1 iff bit 63 of Philox word 0 at counter (0, l*N + i, 1, 0),
@@ -115,15 +120,12 @@ __global__ void k_inv_big(const double *D, double *out, long n) {
 inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 }  // namespace
 
-hipError_t build_exp(int L, double t, double dtau, double *Em, double *Ep, void *Etm, void *Etp,
-                     bool fp64, hipStream_t s) {
+hipError_t build_exp(int L, double t, double dtau, double *Em, double *rm, double *rp, float *rtm,
+                     float *rtp, hipStream_t s) {
+  if (L < 1 || L > 1024) return hipErrorInvalidValue;
   const long n = (long)L * L * L * L;
-  if (fp64 || !Etm)
-    hipLaunchKernelGGL(k_build_exp<double>, dim3(nblocks(n, 256)), dim3(256), 0, s, L, t, dtau, Em, Ep,
-                       (double *)Etm, (double *)Etp);
-  else
-    hipLaunchKernelGGL(k_build_exp<float>, dim3(nblocks(n, 256)), dim3(256), 0, s, L, t, dtau, Em, Ep,
-                       (float *)Etm, (float *)Etp);
+  hipLaunchKernelGGL(k_build_exp, dim3(nblocks(n, 256)), dim3(256), 0, s, L, t, dtau, Em);
+  hipLaunchKernelGGL(k_build_ring, dim3(1), dim3(1024), 0, s, L, t, dtau, rm, rp, rtm, rtp);
   return hipGetLastError();
 }
 

@@ -53,9 +53,26 @@ struct FlipArgs {
 };
 hipError_t flip_slice(const FlipArgs &a, bool fp64, hipStream_t s);
 
-// setup
-hipError_t build_exp(int L, double t, double dtau, double *Em, double *Ep, void *Et_m, void *Et_p,
-                     bool fp64, hipStream_t s);
+// Products with e^{-+dtau K} = R (x) R (R: L x L circulant of the ring
+// propagator r, element type of X):
+//   hop_left:  Y = (R (x) R) diag(ks) X
+//   hop_right: Y = diag(rs) X diag(ks) (R (x) R)
+// X, Y: mats N x N row-major matrices (N = L^2, even L <= 22), Y != X.
+struct HopDesc {
+  int L, mats;
+  const void *X; long sX;
+  void *Y; long sY;
+  const void *r;                 // r(0..L-1)
+  const void *ks; long sks;      // scale of X's rows (left) or columns (right), nullable
+  const void *rs; long srs;      // scale of X's rows, right action only, nullable
+};
+hipError_t hop_left(const HopDesc &d, bool f64, hipStream_t s);
+hipError_t hop_right(const HopDesc &d, bool f64, hipStream_t s);
+
+// setup: dense e^{-dtau K} (FP64) and the ring factors of e^{-dtau K} (rm)
+// and e^{+dtau K} (rp); rtm / rtp (nullable) receive FP32 copies of rm / rp
+hipError_t build_exp(int L, double t, double dtau, double *Em, double *rm, double *rp, float *rtm,
+                     float *rtp, hipStream_t s);
 hipError_t init_field(int8_t *h, int chains, int Lam, int N, uint64_t seed, uint64_t inst,
                       hipStream_t s);
 // out[mat][q - lo][i] = exp(sigma lambda h[chain][q-1][i]), q = lo..hi (FP64)

@@ -59,8 +59,9 @@ struct Shard {
   double U = 0, t = 0, beta = 0, dtau = 0, lambda = 0;
   uint64_t seed = 0;
   // device state
-  double *Em = nullptr, *Ep = nullptr;   // e^{-dtau K}, e^{+dtau K}
-  float *Etm = nullptr, *Etp = nullptr;  // FP32 copies (mixed mode)
+  double *Em = nullptr;                  // e^{-dtau K} (dense, first factor of a block product)
+  double *rm = nullptr, *rp = nullptr;   // ring factors of e^{-dtau K} and e^{+dtau K}
+  float *rtm = nullptr, *rtp = nullptr;  // FP32 copies (mixed mode)
   double *G64 = nullptr;                 // G [2C][N][N] while an FP64 slice is current
   float *G32 = nullptr;                  // G [2C][N][N] while an FP32 slice is current (mixed mode)
   void *Tw = nullptr, *dv = nullptr;     // wrap temporary, slice diagonals: sized for FP64
@@ -136,10 +137,10 @@ struct bss_ctx {
 };
 
 namespace {
-enum KFam { F_FLIP32, F_FLIP64, F_WRAP32, F_WRAP64, F_GEMM64, F_QR_UDV, F_QR_SOLVE, F_ELEM, F_DRIFT, F_MEAS,
-            F_COUNT };
-const char *const FAM_NAMES[F_COUNT] = {"flip_f32", "flip_f64", "wrap_f32", "wrap_f64", "gemm_f64", "qr_udv",
-                                        "qr_solve", "elementwise", "drift_replace", "measure"};
+enum KFam { F_FLIP32, F_FLIP64, F_WRAP32, F_WRAP64, F_HOP64, F_GEMM64, F_QR_UDV, F_QR_SOLVE, F_ELEM, F_DRIFT,
+            F_MEAS, F_COUNT };
+const char *const FAM_NAMES[F_COUNT] = {"flip_f32", "flip_f64", "wrap_f32", "wrap_f64", "hop_f64", "gemm_f64",
+                                        "qr_udv", "qr_solve", "elementwise", "drift_replace", "measure"};
 
 hipEvent_t take_event(bss_ctx *c) {
   if (!c->pool.empty()) { hipEvent_t e = c->pool.back(); c->pool.pop_back(); return e; }
@@ -234,8 +235,9 @@ int shard_count(int C) {
 void layout_shard(Shard &I, bool fp64, Carver &cv) {
   const size_t NN = nn(I), M = (size_t)I.mats;
   I.Em = cv.take<double>(NN);
-  I.Ep = cv.take<double>(NN);
-  if (!fp64) { I.Etm = cv.take<float>(NN); I.Etp = cv.take<float>(NN); }
+  I.rm = cv.take<double>(I.L);
+  I.rp = cv.take<double>(I.L);
+  if (!fp64) { I.rtm = cv.take<float>(I.L); I.rtp = cv.take<float>(I.L); }
   I.G64 = cv.take<double>(M * NN);
   if (!fp64) I.G32 = cv.take<float>(M * NN);
   I.Tw = cv.take<double>(M * NN);
@@ -408,6 +410,16 @@ struct Exec {
     chk(gemm_f64(d, ta, tb, s));
   }
 
+  // out = e^{-dtau K} diag(ks) X (FP64)
+  void hop64(const double *X, double *out, const double *ks, long sks) {
+    HopDesc d{};
+    d.L = I.L; d.mats = I.mats;
+    d.X = X; d.sX = (long)NN(); d.Y = out; d.sY = (long)NN();
+    d.r = I.rm; d.ks = ks; d.sks = sks;
+    Timed tm(c, F_HOP64, s);
+    chk(hop_left(d, true, s));
+  }
+
   // P_b = B_hi ... B_lo (FP64) into Pc(b)
   void block_product(int b) {
     const int lo = b * I.n_stab + 1, hi = std::min((b + 1) * I.n_stab, I.Lam), nq = hi - lo + 1;
@@ -419,8 +431,7 @@ struct Exec {
       chk(scale_columns(I.Em, I.dvD, (long)nq * I.N, bufs[cur], I.mats, I.N, s));
     }
     for (int q = 1; q < nq; ++q) {
-      gemm64(I.Em, false, bufs[cur], false, bufs[cur ^ 1], 0, (long)NN(), I.dvD + (size_t)q * I.N,
-             (long)nq * I.N);
+      hop64(bufs[cur], bufs[cur ^ 1], I.dvD + (size_t)q * I.N, (long)nq * I.N);
       cur ^= 1;
     }
   }
@@ -512,22 +523,25 @@ struct Exec {
   // G <- e^{-dtau K} (D G D^{-1}) e^{+dtau K} in the current G's precision
   void wrap() {
     const bool f64 = I.cur64;
-    const long bs = (long)NN();
-    GemmDesc d = gemm_desc(I.N, I.mats);
-    // T = (D G D^{-1}) e^{+dtau K}
-    d.A = Gcur(); d.sA = bs; d.B = f64 ? (void *)I.Ep : (void *)I.Etp; d.sB = 0; d.C = I.Tw; d.sC = bs;
     const size_t esz = f64 ? 8 : 4;
+    // T = (D G D^{-1}) e^{+dtau K}
+    HopDesc d{};
+    d.L = I.L; d.mats = I.mats;
+    d.X = Gcur(); d.sX = (long)NN(); d.Y = I.Tw; d.sY = (long)NN();
+    d.r = f64 ? (const void *)I.rp : (const void *)I.rtp;
     d.rs = I.dv; d.srs = 2L * I.N;
     d.ks = (char *)I.dv + esz * I.N; d.sks = 2L * I.N;
     {
       Timed tm(c, f64 ? F_WRAP64 : F_WRAP32, s);
-      chk(f64 ? gemm_f64(d, false, false, s) : gemm_f32(d, false, false, s));
+      chk(hop_right(d, f64, s));
     }
     // G = e^{-dtau K} T
-    GemmDesc d2 = gemm_desc(I.N, I.mats);
-    d2.A = f64 ? (void *)I.Em : (void *)I.Etm; d2.sA = 0; d2.B = I.Tw; d2.sB = bs; d2.C = Gcur(); d2.sC = bs;
+    HopDesc d2{};
+    d2.L = I.L; d2.mats = I.mats;
+    d2.X = I.Tw; d2.sX = (long)NN(); d2.Y = Gcur(); d2.sY = (long)NN();
+    d2.r = f64 ? (const void *)I.rm : (const void *)I.rtm;
     Timed tm(c, f64 ? F_WRAP64 : F_WRAP32, s);
-    chk(f64 ? gemm_f64(d2, false, false, s) : gemm_f32(d2, false, false, s));
+    chk(hop_left(d2, f64, s));
   }
 
   void stabilise(int l) {
@@ -587,7 +601,7 @@ struct Exec {
       } else {
         // G(tau_l, 0) = B_l G(tau_{l-1}, 0) = e^{-dtau K} diag(d_l) G(tau_{l-1}, 0)
         chk(slice_scales(I.h, I.C, I.Lam, I.N, l, l, std::exp(I.lambda), std::exp(-I.lambda), I.dvD, s));
-        gemm64(I.Em, false, I.Gt, false, I.Pw, 0, (long)NN(), I.dvD, I.N);
+        hop64(I.Gt, I.Pw, I.dvD, I.N);
         chk(hipMemcpyAsync(I.Gt, I.Pw, sizeof(double) * I.mats * NN(), hipMemcpyDeviceToDevice, s));
       }
       chk(meas_gk(I.ms, I.Gt, I.C, I.L, l, s));
@@ -706,7 +720,7 @@ bss_status create_impl(const bss_instance *in, int n, const bss_options *opt_in,
   if (fork(c) != hipSuccess) return bail(BSS_E_DEVICE);
   for (auto &I : c->sh) {
     Exec x(c, I);
-    x.chk(build_exp(I.L, I.t, I.dtau, I.Em, I.Ep, I.Etm, I.Etp, c->fp64, I.s));
+    x.chk(build_exp(I.L, I.t, I.dtau, I.Em, I.rm, I.rp, I.rtm, I.rtp, I.s));
     x.initialise(true);
     if (x.e != hipSuccess) { c->last_error = hipGetErrorString(x.e); return bail(BSS_E_DEVICE); }
   }
