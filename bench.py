@@ -37,43 +37,52 @@ PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 HBM_PEAK = 8.0e12
 
 # HBM bytes per launch (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0, the scales a
-# 256 MiB device copy gives) from profiles/sweep_16x16_b20_hbm_traffic.md,
-# valid while the kernel's source file is the one the counters were taken on
-# (sha1 prefix); otherwise the traffic is reported as null.
-TRAFFIC = {
+# 256 MiB device copy gives) from the profiles/*hbm_traffic.md summaries of
+# each hopping mode, valid while the kernel's source file is the one the
+# counters were taken on (sha1 prefix); otherwise the traffic is reported as
+# null.
+_COMMON_TRAFFIC = {
     "flip_f64": (1.218e9, "k_flip.hip", "7e46c103ee76"),
     "flip_f32": (5.759e8, "k_flip.hip", "7e46c103ee76"),
     "qr_udv": (2.814e9, "k_qr.hip", "2f24f3565c6e"),
     "qr_solve": (3.468e9, "k_qr.hip", "2f24f3565c6e"),
-    # wraps: one right and one left Kronecker-factor product each (mean of the two)
-    "wrap_f64": (2.726e8, "k_hop.hip", "990a600b01dc"),
-    "wrap_f32": (1.358e8, "k_hop.hip", "990a600b01dc"),
-    "hop_f64": (2.711e8, "k_hop.hip", "990a600b01dc"),
+}
+TRAFFIC = {
+    "dense": dict(_COMMON_TRAFFIC, **{
+        "wrap_f32": (2.046e8, "k_gemm.hip", "b592526b28ba"),
+        "wrap_f64": (6.622e8, "k_gemm.hip", "b592526b28ba"),
+    }),
+    "kronecker": dict(_COMMON_TRAFFIC, **{
+        # wraps: one right and one left Kronecker-factor product each (mean of the two)
+        "wrap_f64": (2.726e8, "k_hop.hip", "990a600b01dc"),
+        "wrap_f32": (1.358e8, "k_hop.hip", "990a600b01dc"),
+        "hop_f64": (2.711e8, "k_hop.hip", "990a600b01dc"),
+    }),
 }
 
 
-def traffic_of(fam: str):
+def traffic_of(fam: str, hopping: str):
     import hashlib
-    if fam not in TRAFFIC:
+    if fam not in TRAFFIC[hopping]:
         return None
-    val, src, sha = TRAFFIC[fam]
+    val, src, sha = TRAFFIC[hopping][fam]
     path = os.path.join(ROOT, "paper_1504_05090_amd", "csrc", src)
     with open(path, "rb") as f:
         return val if hashlib.sha1(f.read()).hexdigest()[:12] == sha else None
 
 
-def family_model(fam: str, N: int, mats: int, chains: int, acc: float, k: int):
+def family_model(fam: str, N: int, mats: int, chains: int, acc: float, k: int, kron: bool = False):
     """Algorithmic work of one launch of a kernel family: (amount, peak per second, bound).
 
     MFMA-bound families count flops against the dense MFMA peak of their
-    dtype; the Kronecker-factor products (wraps, block and measurement
-    products) count the bytes they must move, X read and Y written once, against
-    HBM bandwidth."""
-    if fam in ("wrap_f32", "wrap_f64", "hop_f64"):
+    dtype; the Kronecker-factor products (the wraps with kron, block and
+    measurement products) count the bytes they must move, X read and Y written
+    once, against HBM bandwidth."""
+    if fam == "hop_f64" or (kron and fam in ("wrap_f32", "wrap_f64")):
         esz = 4 if fam.endswith("f32") else 8
         return 2.0 * mats * N * N * esz, HBM_PEAK, "hbm"
-    if fam == "gemm_f64":
-        return 2.0 * N ** 3 * mats, PEAK["f64"], "mfma"        # one batched N x N x N product
+    if fam in ("wrap_f32", "wrap_f64", "gemm_f64"):
+        return 2.0 * N ** 3 * mats, PEAK[fam[-3:]], "mfma"     # one batched N x N x N product
     if fam == "qr_udv":
         return (8.0 / 3.0) * N ** 3 * mats, PEAK["f64"], "mfma"   # Householder R (4/3 N^3) + explicit Q (4/3 N^3)
     if fam == "qr_solve":
@@ -85,9 +94,9 @@ def family_model(fam: str, N: int, mats: int, chains: int, acc: float, k: int):
     return 0.0, None, None
 
 
-def _family_roofline(fam, entry, N, mats, chains, acc, k):
+def _family_roofline(fam, entry, N, mats, chains, acc, k, kron):
     launches, tot = entry
-    amount, peak, bound = family_model(fam, N, mats, chains, acc, k)
+    amount, peak, bound = family_model(fam, N, mats, chains, acc, k, kron)
     if not amount or not launches:
         return {"launches": launches, "avg_launch_ms": tot / max(1, launches)}
     avg_ms = tot / launches
@@ -95,10 +104,10 @@ def _family_roofline(fam, entry, N, mats, chains, acc, k):
             "frac": round(amount / (avg_ms / 1e3) / peak, 4)}
 
 
-def run_path(bss, inst, precision, k, n_stab, steps, warmup, fp32_slices=0, profile=False):
+def run_path(bss, inst, precision, k, n_stab, steps, warmup, fp32_slices=0, profile=False, flags=0):
     import torch
     stream = torch.cuda.Stream()
-    flags = bss.FLAG_PROFILE if profile else 0
+    flags |= bss.FLAG_PROFILE if profile else 0
     ctx = bss.Context([inst], precision=precision, delay_k=k, n_stab=n_stab, flags=flags, stream=stream,
                       fp32_slices=fp32_slices)
     ctx.sweep(warmup)
@@ -148,6 +157,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--hopping", choices=["dense", "kronecker"], default="dense",
+                    help="how the headline path applies e^{-+dtau K}: dense MFMA GEMMs (the benchmark's "
+                         "definition) or the Kronecker-factor products")
+    ap.add_argument("--no-kronecker", action="store_true",
+                    help="skip the Kronecker-hopping line beside a dense headline")
     ap.add_argument("--cpu-chains", type=int, default=0, help="oracle chains for the CPU baseline (0 = cores)")
     ap.add_argument("--no-batch", action="store_true", help="skip the multigrid-batch measurement")
     ap.add_argument("--no-oracle-check", action="store_true", help="skip the sampled comparison with the oracle")
@@ -182,7 +196,9 @@ def main():
     print(f"[bench] 16x16 beta=20 dtau=0.5: {C} chains, k={k}, n_stab={n_stab}, {updates_per_step} updates/step, "
           f"{args.warmup} warm-up + {args.steps} timed sweeps", file=sys.stderr, flush=True)
 
-    ctx, ms, st, _ = run_path(bss, inst, "mixed", k, n_stab, args.steps, args.warmup)
+    kron_head = args.hopping == "kronecker"
+    hflags = bss.FLAG_KRONECKER_HOPPING if kron_head else 0
+    ctx, ms, st, _ = run_path(bss, inst, "mixed", k, n_stab, args.steps, args.warmup, flags=hflags)
     value = updates_per_step * args.steps / (ms / 1e3)
     mixed = summary(st)
     m32 = mixed["fp32_slices"]
@@ -210,7 +226,7 @@ def main():
     fp64 = None
     fp64_value = None
     if not args.no_fp64:
-        ctx64, ms64, st64, _ = run_path(bss, inst, "fp64", k, n_stab, args.steps, args.warmup)
+        ctx64, ms64, st64, _ = run_path(bss, inst, "fp64", k, n_stab, args.steps, args.warmup, flags=hflags)
         fp64_value = updates_per_step * args.steps / (ms64 / 1e3)
         fp64 = dict(summary(st64), value=fp64_value, ms_per_step=ms64 / args.steps)
         print(f"[bench] fp64: {ms64 / args.steps:.2f} ms/step, {fp64_value:.4g} updates/s, {summary(st64)}",
@@ -218,7 +234,7 @@ def main():
         del ctx64
         # every slice in FP32: faster, but its drift is far outside any bound
         ctx32, ms32, st32, _ = run_path(bss, inst, "mixed", k, n_stab, max(2, args.steps // 2), 2,
-                                        fp32_slices=n_stab)
+                                        fp32_slices=n_stab, flags=hflags)
         all32 = dict(summary(st32), value=updates_per_step * max(2, args.steps // 2) / (ms32 / 1e3),
                      ms_per_step=ms32 / max(2, args.steps // 2))
         print(f"[bench] all slices FP32 (not valid at this coupling): {all32}", file=sys.stderr, flush=True)
@@ -226,31 +242,48 @@ def main():
     else:
         all32 = None
 
+    # the same sweeps with e^{-+dtau K} applied through its Kronecker factors
+    # (an option of the library; the headline applies it as dense MFMA GEMMs)
+    kron = None
+    if not args.no_kronecker and not kron_head:
+        ctxk, msk, stk, _ = run_path(bss, inst, "mixed", k, n_stab, args.steps, args.warmup,
+                                     flags=bss.FLAG_KRONECKER_HOPPING)
+        kval = updates_per_step * args.steps / (msk / 1e3)
+        kron = dict(summary(stk), value=kval, ms_per_step=msk / args.steps, speedup_vs_headline=kval / value)
+        del ctxk
+        if not args.no_fp64:
+            ctxk, msk, stk, _ = run_path(bss, inst, "fp64", k, n_stab, args.steps, args.warmup,
+                                         flags=bss.FLAG_KRONECKER_HOPPING)
+            kron["fp64_path"] = dict(summary(stk), value=updates_per_step * args.steps / (msk / 1e3),
+                                     ms_per_step=msk / args.steps)
+            del ctxk
+        print(f"[bench] Kronecker hopping: {kron}", file=sys.stderr, flush=True)
+
     # per-kernel-family HIP-event timings of the headline path
     psteps = max(2, args.steps // 2)
-    ctxp, msp, stp, prof = run_path(bss, inst, "mixed", k, n_stab, psteps, 2, profile=True)
+    ctxp, msp, stp, prof = run_path(bss, inst, "mixed", k, n_stab, psteps, 2, profile=True, flags=hflags)
     del ctxp
     acc = stp["accepted"] / max(1, stp["proposals"])
     mats = 2 * C
-    fams = sorted(prof.items(), key=lambda kv: -kv[1][1])
+    fams = sorted(((f, v) for f, v in prof.items() if v[0] > 0), key=lambda kv: -kv[1][1])
     bound_time = 0.0
     for fam, (launches, tot) in fams:
-        amount, pk, _ = family_model(fam, N, mats, C, acc, k)
+        amount, pk, _ = family_model(fam, N, mats, C, acc, k, kron_head)
         if amount:
             bound_time += amount * launches / pk
     dom, (launches, tot) = fams[0]
     avg_ms = tot / max(1, launches)
-    amount, peak, bound = family_model(dom, N, mats, C, acc, k)
+    amount, peak, bound = family_model(dom, N, mats, C, acc, k, kron_head)
     achieved = amount / (avg_ms / 1e3) if amount else None
     scale = 1e9 if bound == "hbm" else 1e12
     roofline = {"kernel": dom, "bound": bound, "achieved": achieved / scale if achieved else None,
                 "peak": peak / scale if peak else None, "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
-                "frac": (achieved / peak) if (achieved and peak) else None, "traffic": traffic_of(dom),
+                "frac": (achieved / peak) if (achieved and peak) else None, "traffic": traffic_of(dom, args.hopping),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "avg_launch_ms": avg_ms, "launches": launches,
                 "bound_time_fraction_of_sweep": bound_time / (msp / 1e3),
                 "breakdown_ms_per_step": {kf: round(v[1] / psteps, 3) for kf, v in fams},
-                "families": {kf: _family_roofline(kf, v, N, mats, C, acc, k) for kf, v in fams}}
+                "families": {kf: _family_roofline(kf, v, N, mats, C, acc, k, kron_head) for kf, v in fams}}
     print(f"[bench] profile ({msp / psteps:.2f} ms/step): {roofline['breakdown_ms_per_step']}", file=sys.stderr,
           flush=True)
 
@@ -285,13 +318,15 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic (Markov chains from seeded Philox fields)",
         "config": {"workload": f"16x16 Hubbard BSS-QMC sweep, t=0.25, U=2, beta=20, dtau=0.5 (Lambda=40), "
-                               f"{C} chains, k={k}, n_stab={n_stab}, FP32 in the last {m32} slices of each block",
+                               f"{C} chains, k={k}, n_stab={n_stab}, FP32 in the last {m32} slices of each block, "
+                               + ("e^{-+dtau K} through its Kronecker factors" if kron_head
+                                  else "wraps and block products as dense MFMA GEMMs"),
                    "L": p["L"], "chains": C, "beta": p["beta"], "dtau": p["dtau"], "U": p["U"], "k": k,
-                   "n_stab": n_stab, "fp32_slices": m32},
+                   "n_stab": n_stab, "fp32_slices": m32, "hopping": args.hopping},
         "drift_rel_max": mixed["drift_rel_max"], "drift_rel_mean": mixed["drift_rel_mean"],
         "max_dG_vs_oracle_sweep_end": max_dg, "acceptance": mixed["acceptance"],
         "fp64_path": fp64, "speedup_vs_fp64": (value / fp64_value) if fp64_value else None,
-        "all_fp32_bulk": all32, "multigrid_batch": batch,
+        "all_fp32_bulk": all32, "kronecker_hopping": kron, "multigrid_batch": batch,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -84,6 +84,16 @@ typedef enum {
                                       hipGraph on first use and replays it (measured
                                       sweeps and PROFILE launch directly)            */
 #define BSS_FLAG_PROFILE 0x8u      /* time every kernel launch with HIP events        */
+#define BSS_FLAG_KRONECKER_HOPPING 0x10u
+                                   /* apply e^{-+dtau K} through its Kronecker factors
+                                      in the wraps, the block products and the
+                                      G(tau, 0) products: the hopping of eq. (1) on the
+                                      periodic square lattice splits into commuting x
+                                      and y rings, so e^{-s K} = R (x) R with R the
+                                      L x L circulant of the ring propagator.  Same
+                                      matrices up to rounding, 4 L^5 instead of 2 L^6
+                                      multiply-adds per product, bound by HBM
+                                      bandwidth.  Default: dense MFMA GEMMs.          */
 
 typedef struct {
   uint32_t struct_size;  /* sizeof(bss_options)                                    */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libbssqmc.so")
 BSS_OK, BSS_E_INVALID_ARG, BSS_E_UNSUPPORTED, BSS_E_OUT_OF_MEMORY, BSS_E_DEVICE, BSS_E_NUMERICAL, BSS_E_STATE = range(7)
 PREC = {"fp64": 0, "mixed": 1}
 FLAG_RECORD_TRACE, FLAG_REPLAY_TRACE, FLAG_NO_GRAPH, FLAG_PROFILE = 0x1, 0x2, 0x4, 0x8
+FLAG_KRONECKER_HOPPING = 0x10
 
 # every entry point declared in include/bssqmc.h
 EXPORTS = [

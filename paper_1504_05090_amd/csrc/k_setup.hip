@@ -41,14 +41,18 @@ __device__ double ring_propagator(int d, int L, double x, bool alternate) {
   return sum;
 }
 
-__global__ void k_build_exp(int L, double t, double dtau, double *Em) {
+__global__ void k_build_exp(int L, double t, double dtau, double *Em, double *Ep, float *Etm, float *Etp) {
   const int N = L * L;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long)N * N) return;
   const int i = (int)(e / N), j = (int)(e % N);
   const int dx = ((i % L) - (j % L) + L) % L, dy = ((i / L) - (j / L) + L) % L;
   const double x = 2.0 * dtau * t;
-  Em[e] = ring_propagator(dx, L, x, false) * ring_propagator(dy, L, x, false);
+  const double sm = ring_propagator(dx, L, x, false) * ring_propagator(dy, L, x, false);
+  const double sp = ring_propagator(dx, L, x, true) * ring_propagator(dy, L, x, true);
+  Em[e] = sm;
+  Ep[e] = sp;
+  if (Etm) { Etm[e] = (float)sm; Etp[e] = (float)sp; }
 }
 
 __global__ void k_build_ring(int L, double t, double dtau, double *rm, double *rp, float *rtm, float *rtp) {
@@ -120,11 +124,11 @@ __global__ void k_inv_big(const double *D, double *out, long n) {
 inline unsigned nblocks(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 }  // namespace
 
-hipError_t build_exp(int L, double t, double dtau, double *Em, double *rm, double *rp, float *rtm,
-                     float *rtp, hipStream_t s) {
+hipError_t build_exp(int L, double t, double dtau, double *Em, double *Ep, float *Etm, float *Etp, double *rm,
+                     double *rp, float *rtm, float *rtp, hipStream_t s) {
   if (L < 1 || L > 1024) return hipErrorInvalidValue;
   const long n = (long)L * L * L * L;
-  hipLaunchKernelGGL(k_build_exp, dim3(nblocks(n, 256)), dim3(256), 0, s, L, t, dtau, Em);
+  hipLaunchKernelGGL(k_build_exp, dim3(nblocks(n, 256)), dim3(256), 0, s, L, t, dtau, Em, Ep, Etm, Etp);
   hipLaunchKernelGGL(k_build_ring, dim3(1), dim3(1024), 0, s, L, t, dtau, rm, rp, rtm, rtp);
   return hipGetLastError();
 }

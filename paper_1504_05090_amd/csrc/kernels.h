@@ -69,10 +69,11 @@ struct HopDesc {
 hipError_t hop_left(const HopDesc &d, bool f64, hipStream_t s);
 hipError_t hop_right(const HopDesc &d, bool f64, hipStream_t s);
 
-// setup: dense e^{-dtau K} (FP64) and the ring factors of e^{-dtau K} (rm)
-// and e^{+dtau K} (rp); rtm / rtp (nullable) receive FP32 copies of rm / rp
-hipError_t build_exp(int L, double t, double dtau, double *Em, double *rm, double *rp, float *rtm,
-                     float *rtp, hipStream_t s);
+// setup: dense e^{-dtau K} and e^{+dtau K} (FP64; Etm / Etp, nullable,
+// receive FP32 copies) and their ring factors rm and rp (rtm / rtp,
+// nullable: FP32 copies)
+hipError_t build_exp(int L, double t, double dtau, double *Em, double *Ep, float *Etm, float *Etp, double *rm,
+                     double *rp, float *rtm, float *rtp, hipStream_t s);
 hipError_t init_field(int8_t *h, int chains, int Lam, int N, uint64_t seed, uint64_t inst,
                       hipStream_t s);
 // out[mat][q - lo][i] = exp(sigma lambda h[chain][q-1][i]), q = lo..hi (FP64)

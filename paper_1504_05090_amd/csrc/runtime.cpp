@@ -59,8 +59,9 @@ struct Shard {
   double U = 0, t = 0, beta = 0, dtau = 0, lambda = 0;
   uint64_t seed = 0;
   // device state
-  double *Em = nullptr;                  // e^{-dtau K} (dense, first factor of a block product)
-  double *rm = nullptr, *rp = nullptr;   // ring factors of e^{-dtau K} and e^{+dtau K}
+  double *Em = nullptr, *Ep = nullptr;   // e^{-dtau K}, e^{+dtau K}
+  float *Etm = nullptr, *Etp = nullptr;  // FP32 copies (mixed mode)
+  double *rm = nullptr, *rp = nullptr;   // their ring factors (Kronecker hopping)
   float *rtm = nullptr, *rtp = nullptr;  // FP32 copies (mixed mode)
   double *G64 = nullptr;                 // G [2C][N][N] while an FP64 slice is current
   float *G32 = nullptr;                  // G [2C][N][N] while an FP32 slice is current (mixed mode)
@@ -235,6 +236,8 @@ int shard_count(int C) {
 void layout_shard(Shard &I, bool fp64, Carver &cv) {
   const size_t NN = nn(I), M = (size_t)I.mats;
   I.Em = cv.take<double>(NN);
+  I.Ep = cv.take<double>(NN);
+  if (!fp64) { I.Etm = cv.take<float>(NN); I.Etp = cv.take<float>(NN); }
   I.rm = cv.take<double>(I.L);
   I.rp = cv.take<double>(I.L);
   if (!fp64) { I.rtm = cv.take<float>(I.L); I.rtp = cv.take<float>(I.L); }
@@ -410,8 +413,15 @@ struct Exec {
     chk(gemm_f64(d, ta, tb, s));
   }
 
-  // out = e^{-dtau K} diag(ks) X (FP64)
+  bool kron() const { return (c->opt.flags & BSS_FLAG_KRONECKER_HOPPING) != 0; }
+
+  // out = e^{-dtau K} diag(ks) X (FP64), as a dense GEMM or through the
+  // Kronecker factors
   void hop64(const double *X, double *out, const double *ks, long sks) {
+    if (!kron()) {
+      gemm64(I.Em, false, X, false, out, 0, (long)NN(), ks, sks);
+      return;
+    }
     HopDesc d{};
     d.L = I.L; d.mats = I.mats;
     d.X = X; d.sX = (long)NN(); d.Y = out; d.sY = (long)NN();
@@ -522,6 +532,7 @@ struct Exec {
 
   // G <- e^{-dtau K} (D G D^{-1}) e^{+dtau K} in the current G's precision
   void wrap() {
+    if (!kron()) return wrap_gemm();
     const bool f64 = I.cur64;
     const size_t esz = f64 ? 8 : 4;
     // T = (D G D^{-1}) e^{+dtau K}
@@ -542,6 +553,27 @@ struct Exec {
     d2.r = f64 ? (const void *)I.rm : (const void *)I.rtm;
     Timed tm(c, f64 ? F_WRAP64 : F_WRAP32, s);
     chk(hop_left(d2, f64, s));
+  }
+
+  // the same wrap as two batched MFMA GEMMs with the dense exponentials
+  void wrap_gemm() {
+    const bool f64 = I.cur64;
+    const long bs = (long)NN();
+    GemmDesc d = gemm_desc(I.N, I.mats);
+    // T = (D G D^{-1}) e^{+dtau K}
+    d.A = Gcur(); d.sA = bs; d.B = f64 ? (void *)I.Ep : (void *)I.Etp; d.sB = 0; d.C = I.Tw; d.sC = bs;
+    const size_t esz = f64 ? 8 : 4;
+    d.rs = I.dv; d.srs = 2L * I.N;
+    d.ks = (char *)I.dv + esz * I.N; d.sks = 2L * I.N;
+    {
+      Timed tm(c, f64 ? F_WRAP64 : F_WRAP32, s);
+      chk(f64 ? gemm_f64(d, false, false, s) : gemm_f32(d, false, false, s));
+    }
+    // G = e^{-dtau K} T
+    GemmDesc d2 = gemm_desc(I.N, I.mats);
+    d2.A = f64 ? (void *)I.Em : (void *)I.Etm; d2.sA = 0; d2.B = I.Tw; d2.sB = bs; d2.C = Gcur(); d2.sC = bs;
+    Timed tm(c, f64 ? F_WRAP64 : F_WRAP32, s);
+    chk(f64 ? gemm_f64(d2, false, false, s) : gemm_f32(d2, false, false, s));
   }
 
   void stabilise(int l) {
@@ -720,7 +752,7 @@ bss_status create_impl(const bss_instance *in, int n, const bss_options *opt_in,
   if (fork(c) != hipSuccess) return bail(BSS_E_DEVICE);
   for (auto &I : c->sh) {
     Exec x(c, I);
-    x.chk(build_exp(I.L, I.t, I.dtau, I.Em, I.rm, I.rp, I.rtm, I.rtp, I.s));
+    x.chk(build_exp(I.L, I.t, I.dtau, I.Em, I.Ep, I.Etm, I.Etp, I.rm, I.rp, I.rtm, I.rtp, I.s));
     x.initialise(true);
     if (x.e != hipSuccess) { c->last_error = hipGetErrorString(x.e); return bail(BSS_E_DEVICE); }
   }

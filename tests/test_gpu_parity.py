@@ -93,9 +93,10 @@ def test_free_running_sweeps(L, U, beta, dtau, k, n_stab):
     assert st["drift_max"] <= 100 * max(odrift, 1e-13)
 
 
+@pytest.mark.parametrize("hopping", [0, bss.FLAG_KRONECKER_HOPPING], ids=["dense", "kronecker"])
 @pytest.mark.parametrize("L,U,beta,dtau,k,n_stab", [CASES[0], CASES[1]])
-def test_slice_by_slice(L, U, beta, dtau, k, n_stab):
-    g = ctx(L, U, beta, dtau, 1, k=k, n_stab=n_stab)
+def test_slice_by_slice(L, U, beta, dtau, k, n_stab, hopping):
+    g = ctx(L, U, beta, dtau, 1, k=k, n_stab=n_stab, flags=hopping)
     o = oracle.Chain(L, U, T, beta, dtau, BASE_SEED, 0, 0, n_stab)
     lam = o.Lam
     for step in range(2 * lam):
@@ -177,7 +178,8 @@ def one_slice_bound(n_acc, f_max, g_max, lam, dtau, t):
     return max(1, n_acc) * 2.0 ** -53 * (1.0 + f_max * (1.0 + g_max)) * math.exp(2 * lam + 8 * dtau * t)
 
 
-def test_headline_lattice_fp64_slice_by_slice():
+@pytest.mark.parametrize("hopping", [0, bss.FLAG_KRONECKER_HOPPING], ids=["dense", "kronecker"])
+def test_headline_lattice_fp64_slice_by_slice(hopping):
     """Headline lattice (16 x 16, beta = 20, dtau = 0.5), FP64, the oracle's
     decisions for the first 7 slices replayed.  Before every slice the oracle
     is set to the GPU's G; the GPU's G after the slice must then agree with
@@ -198,7 +200,7 @@ def test_headline_lattice_fp64_slice_by_slice():
     tr[: n * N] = o.step_slices(n, record=True)
     r = oracle.Chain(L, 2.0, T, beta, dtau, BASE_SEED, 0, 0, n_stab)
     lam = r.lam
-    g = ctx(L, 2.0, beta, dtau, 1, precision="fp64", k=k, n_stab=n_stab, flags=bss.FLAG_REPLAY_TRACE,
+    g = ctx(L, 2.0, beta, dtau, 1, precision="fp64", k=k, n_stab=n_stab, flags=bss.FLAG_REPLAY_TRACE | hopping,
             trace_sweeps=1)
     g.set_trace(tr, 1)
     for m in range(n):
@@ -253,9 +255,11 @@ GOLDEN_L16 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", 
 MIXED_BOUND = 1e-3
 
 
-@pytest.mark.parametrize("precision,n_stab,m32", [("fp64", 4, 0), ("fp64", 8, 0), ("mixed", 8, 0), ("mixed", 8, 1),
-                                                   ("mixed", 4, 0), ("mixed", 2, 0)])
-def test_headline_lattice_equilibrated_forced_history(precision, n_stab, m32):
+@pytest.mark.parametrize("precision,n_stab,m32,hopping",
+                         [("fp64", 4, 0, 0), ("fp64", 8, 0, 0), ("mixed", 8, 0, 0), ("mixed", 8, 1, 0),
+                          ("mixed", 4, 0, 0), ("mixed", 2, 0, 0),
+                          ("fp64", 8, 0, bss.FLAG_KRONECKER_HOPPING), ("mixed", 8, 0, bss.FLAG_KRONECKER_HOPPING)])
+def test_headline_lattice_equilibrated_forced_history(precision, n_stab, m32, hopping):
     """16 x 16, beta = 20 from an equilibrated field written by the oracle
     (tests/golden/make_fields.py): the oracle's decisions for 8 slices are
     replayed and G is compared after every slice.  Between recomputations the
@@ -265,7 +269,7 @@ def test_headline_lattice_equilibrated_forced_history(precision, n_stab, m32):
     f0 = np.load(GOLDEN_L16)
     o = oracle.Chain(16, 2.0, T, 20.0, 0.5, BASE_SEED, 0, 0, n_stab)
     o.set_field(f0)
-    g = ctx(16, 2.0, 20.0, 0.5, 1, precision=precision, k=32, n_stab=n_stab, flags=bss.FLAG_REPLAY_TRACE,
+    g = ctx(16, 2.0, 20.0, 0.5, 1, precision=precision, k=32, n_stab=n_stab, flags=bss.FLAG_REPLAY_TRACE | hopping,
             trace_sweeps=1, fp32_slices=m32)
     g.set_field(f0)
     n_sl = 8
@@ -436,8 +440,9 @@ def test_checkpoint_resume_continues_the_chain():
     assert c.stats()["sweeps"] == 4
 
 
-@pytest.mark.parametrize("precision,m32", [("fp64", 0), ("mixed", 1)])
-def test_graph_replays_match_direct_launches(precision, m32):
+@pytest.mark.parametrize("precision,m32,hopping", [("fp64", 0, 0), ("mixed", 1, 0),
+                                                   ("mixed", 1, bss.FLAG_KRONECKER_HOPPING)])
+def test_graph_replays_match_direct_launches(precision, m32, hopping):
     """A sweep captured into a hipGraph and replayed gives bit for bit what
     direct launches give: the graph context and a NO_GRAPH twin are swept
     side by side, with direct-launch sweeps (step_slices), synchronisations
@@ -445,10 +450,10 @@ def test_graph_replays_match_direct_launches(precision, m32):
     import torch
     L, U, beta, dtau, C = 6, 2.0, 4.0, 0.5, 4
     inst = dict(L=L, U=U, t=T, beta=beta, dtau=dtau, seed=BASE_SEED, n_chains=C)
-    print(f"[gpu] graph vs direct: 6x6 {precision} fp32_slices={m32}", flush=True)
+    print(f"[gpu] graph vs direct: 6x6 {precision} fp32_slices={m32} flags={hopping}", flush=True)
     kw = dict(precision=precision, delay_k=8, n_stab=3, fp32_slices=m32)
-    a = bss.Context([inst], stream=torch.cuda.Stream(), **kw)
-    b = bss.Context([inst], stream=torch.cuda.Stream(), flags=bss.FLAG_NO_GRAPH, **kw)
+    a = bss.Context([inst], stream=torch.cuda.Stream(), flags=hopping, **kw)
+    b = bss.Context([inst], stream=torch.cuda.Stream(), flags=bss.FLAG_NO_GRAPH | hopping, **kw)
     lam = int(round(beta / dtau))
 
     def same(tag):
@@ -533,12 +538,29 @@ def test_autotuner_respects_the_drift_bound():
         assert np.array_equal(g.field(0, c), o.field())
 
 
-@pytest.mark.parametrize("L,k,n_stab", [(18, 32, 2), (20, 16, 4)])
-def test_lattices_above_256_sites(L, k, n_stab):
+@pytest.mark.parametrize("L,k,n_stab,hopping", [(18, 32, 2, 0), (20, 16, 4, 0),
+                                                (20, 16, 4, bss.FLAG_KRONECKER_HOPPING)])
+def test_lattices_above_256_sites(L, k, n_stab, hopping):
     """N = 324 and 400: the one-lane-per-site flip kernel (N > 256) and the
     narrow-panel QR follow the oracle chain: fields bit for bit, G to 1e-10."""
     beta, dtau = 2.0, 0.5
-    g = ctx(L, 2.0, beta, dtau, 2, k=k, n_stab=n_stab)
+    g = ctx(L, 2.0, beta, dtau, 2, k=k, n_stab=n_stab, flags=hopping)
+    g.sweep(1)
+    for c in range(2):
+        o = oracle.Chain(L, 2.0, T, beta, dtau, BASE_SEED, 0, c, n_stab)
+        o.sweep(1)
+        assert np.array_equal(g.field(0, c), o.field()), c
+        for s in range(2):
+            assert rel(g.green(0, c, s), o.green(s)) < 1e-10, (c, s)
+
+
+@pytest.mark.parametrize("L", [2, 8, 12, 14, 22])
+def test_kronecker_hopping_lattice_sizes(L):
+    """The Kronecker-factor products are instantiated per lattice side (even
+    L up to 22, N <= 484); the sides not covered by the tests above free-run
+    one sweep against the oracle chain: fields bit for bit, G to 1e-10."""
+    beta, dtau, n_stab = 2.0, 0.5, 2
+    g = ctx(L, 2.0, beta, dtau, 2, k=0, n_stab=n_stab, flags=bss.FLAG_KRONECKER_HOPPING)
     g.sweep(1)
     for c in range(2):
         o = oracle.Chain(L, 2.0, T, beta, dtau, BASE_SEED, 0, c, n_stab)
