@@ -60,19 +60,22 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
   };
   auto a_lds = [&](int buf, int ii, int kk) -> T & { return TA ? As[buf][kk][ii] : As[buf][ii][kk]; };
   auto b_lds = [&](int buf, int kk, int jj) -> T & { return TB ? Bs[buf][jj][kk] : Bs[buf][kk][jj]; };
-  T ra[EA], rb[EB];
+  // A's column scale is fetched beside A and applied when the chunk is
+  // stashed, so no fetched value is consumed before the current chunk's MFMAs
+  T ra[EA], rk[EA], rb[EB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       int ii, kk;
       a_index(e, ii, kk);
       const int gi = i0 + ii, gk = k0 + kk;
-      T v = 0;
+      T v = 0, sk = 0;
       if (gi < d.M && gk < d.K) {
         v = TA ? A[(long)gk * d.lda + gi] : A[(long)gi * d.lda + gk];
-        if (ks) v *= ks[gk];
+        if (ks) sk = ks[gk];
       }
       ra[e] = v;
+      rk[e] = sk;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
     for (int e = 0; e < EA; ++e) {
       int ii, kk;
       a_index(e, ii, kk);
-      a_lds(buf, ii, kk) = ra[e];
+      a_lds(buf, ii, kk) = ks ? ra[e] * rk[e] : ra[e];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
