@@ -44,15 +44,20 @@ __device__ unsigned long long qr_phase_ticks[16];
 #define QR_TICK_INIT do {} while (0)
 #endif
 
-// per-shape constants: panel width NB, chunk width CW, max row tiles per wave
-template <int NB_, int CW_, int RTW_> struct Shape {
+// per-shape constants: panel width NB, chunk width CW, max row tiles per wave;
+// COLS: block reflectors applied by whole-column tiles per wavefront
+// (apply_cols, every row of a tile in registers), else by row tiles
+// (apply_block)
+template <int NB_, int CW_, int RTW_, bool COLS_> struct Shape {
   static constexpr int NB = NB_, CW = CW_, RTW = RTW_;
+  static constexpr bool COLS = COLS_;
   static constexpr int LDV = NB + 1;
   static constexpr int CT = CW / 16;   // column tiles per chunk
   static constexpr int WT = NB / 16;   // row tiles of W
+  static constexpr int MT = 4 * RTW;   // row tiles of the largest matrix
 };
-typedef Shape<32, 64, 4> ShapeS;   // N <= 256
-typedef Shape<16, 32, 8> ShapeL;   // N <= 512
+typedef Shape<32, 64, 4, true> ShapeS;    // N <= 256
+typedef Shape<16, 32, 8, false> ShapeL;   // N <= 512
 
 struct Lds {
   double *V;      // [mr][LDV] panel / clean reflectors
@@ -123,10 +128,17 @@ __device__ void panel_factor(const Lds &s, int m, int w, int *swp) {
   }
   for (int j = 0; j < w; ++j) {
     if (PIVOT) {
-      int p = j;
-      double best = s.pn[j];
-      for (int q = j + 1; q < w; ++q)
-        if (s.pn[q] > best) { best = s.pn[q]; p = q; }
+      // every wavefront finds the first column of largest norm among j..w-1
+      // (lane q holds column j + q; w <= 64)
+      const int lane = t & 63;
+      double best = (j + lane < w) ? s.pn[j + lane] : -1.0;
+      int p = j + lane;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int op = __shfl_xor(p, o, 64);
+        if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
+      }
       __syncthreads();   // every thread has read pn before thread 0 permutes it
       if (p != j) {
         for (int r = t; r < m; r += QT) {
@@ -373,6 +385,116 @@ __device__ void apply_block(const Lds &s, double *X, long ldx, int r0, int m, in
   }
 }
 
+// The same product for N <= 16 MT, one 16-column tile per wavefront at a
+// time.  The tile is held over all rows in accumulator layout (register r of
+// lane (lq, l16): row 16 rt + lq + 4 r, column l16), which is also the layout
+// of an MFMA B operand whose k-step st takes register st.  So W = V^T C,
+// W2 = op(T) W and C -= V W2 all run on MFMA from the wavefront's own
+// registers; only V and T are read from LDS, and no data passes between
+// wavefronts.  With NORMS each column's squared norm over rows >= nskip is
+// summed within the wavefront.
+template <class S, bool TRANS_T, bool NORMS>
+__device__ void apply_cols(const Lds &s, double *X, long ldx, int r0, int m, int mr, int c0, int c1, int nskip) {
+  constexpr int LDV = S::LDV, NB = S::NB, WT = S::WT, MT = S::MT;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  const int rtiles = mr / 16;
+  for (int cc = c0 + 16 * wv; cc < c1; cc += 16 * (QT / 64)) {
+    const int col = cc + l16;
+    const bool cok = col < c1;
+    // rows are walked with one running offset (the empty asm keeps the
+    // compiler from materialising all 4 MT row addresses at once)
+    const long step = 4 * ldx, off0 = (long)(r0 + lq) * ldx + col;
+    M64::acc_t cr[MT];
+    {
+      long off = off0;
+#pragma unroll
+      for (int rt = 0; rt < MT; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * rt + lq + 4 * r;
+          cr[rt][r] = (rt < rtiles && row < m && cok) ? X[off] : 0.0;
+          off += step;
+          asm volatile("" : "+v"(off));
+        }
+    }
+    // W = V^T C  (NB x 16)
+    M64::acc_t w[WT];
+#pragma unroll
+    for (int i = 0; i < WT; ++i) w[i] = M64::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) {
+      if (rt < rtiles) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int k = 16 * rt + 4 * st + lq;
+#pragma unroll
+          for (int i = 0; i < WT; ++i) w[i] = M64::mac(s.V[k * LDV + 16 * i + l16], cr[rt][st], w[i]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);   // keep one row tile's operands live at a time
+    }
+    // W2 = op(T) W  (T upper triangular, zero below the diagonal)
+    M64::acc_t w2[WT];
+#pragma unroll
+    for (int i = 0; i < WT; ++i) w2[i] = M64::acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int it = 0; it < WT; ++it)
+#pragma unroll
+      for (int kt = 0; kt < WT; ++kt)
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int i = 16 * it + l16, k = 16 * kt + 4 * st + lq;
+          w2[it] = M64::mac(TRANS_T ? s.T[k * NB + i] : s.T[i * NB + k], w[kt][st], w2[it]);
+        }
+    // C -= V W2
+#pragma unroll
+    for (int i = 0; i < WT; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) w2[i][r] = -w2[i][r];
+#pragma unroll
+    for (int rt = 0; rt < MT; ++rt) {
+      if (rt < rtiles) {
+#pragma unroll
+        for (int kt = 0; kt < WT; ++kt)
+#pragma unroll
+          for (int st = 0; st < 4; ++st)
+            cr[rt] = M64::mac(s.V[(16 * rt + l16) * LDV + 16 * kt + 4 * st + lq], w2[kt][st], cr[rt]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    double nrm = 0.0;
+    {
+      long off = off0;
+#pragma unroll
+      for (int rt = 0; rt < MT; ++rt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * rt + lq + 4 * r;
+          if (rt < rtiles && row < m && cok) {
+            X[off] = cr[rt][r];
+            if (NORMS && row >= nskip) nrm += cr[rt][r] * cr[rt][r];
+          }
+          off += step;
+          asm volatile("" : "+v"(off));
+        }
+      }
+    }
+    if (NORMS) {
+      nrm += __shfl_xor(nrm, 16, 64);
+      nrm += __shfl_xor(nrm, 32, 64);
+      if (lq == 0 && cok) s.norms[col] = nrm;
+    }
+  }
+  __syncthreads();
+}
+
+template <class S, bool TRANS_T, bool NORMS>
+__device__ void apply(const Lds &s, double *X, long ldx, int r0, int m, int mr, int c0, int c1, int nskip) {
+  if constexpr (S::COLS) apply_cols<S, TRANS_T, NORMS>(s, X, ldx, r0, m, mr, c0, c1, nskip);
+  else apply_block<S, TRANS_T, NORMS>(s, X, ldx, r0, m, mr, c0, c1, nskip);
+}
+
 // Swap the NB remaining columns of largest current norm (ties: lower physical
 // index first) into positions [c0, c0 + w), in order of decreasing norm; the
 // columns they displace take the vacated positions (k-th displaced column,
@@ -487,9 +609,9 @@ __device__ void factor(const Lds &s, double *A, double *Tsave, double *scratch, 
     build_T<S>(s, m, w, mr);
     for (int e = threadIdx.x; e < NB * NB; e += QT) Tsave[(long)(c0 / NB) * NB * NB + e] = s.T[e];
     QR_TICK(4);
-    if (c0 + w < N) apply_block<S, true, PIVOT>(s, A, N, c0, m, mr, c0 + w, N, w);
+    if (c0 + w < N) apply<S, true, PIVOT>(s, A, N, c0, m, mr, c0 + w, N, w);
     QR_TICK(5);
-    if (B) apply_block<S, true, false>(s, B, nrhs, c0, m, mr, 0, nrhs, 0);
+    if (B) apply<S, true, false>(s, B, nrhs, c0, m, mr, 0, nrhs, 0);
     QR_TICK(6);
   }
 }
@@ -533,7 +655,7 @@ __global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long 
     for (int e = t; e < S::NB * S::NB; e += QT) s.T[e] = Ts[(long)p * S::NB * S::NB + e];
     __syncthreads();
     QR_TICK(7);
-    apply_block<S, false, false>(s, U, N, c0, m, mr, c0, N, 0);
+    apply<S, false, false>(s, U, N, c0, m, mr, c0, N, 0);
     QR_TICK(8);
   }
 }
