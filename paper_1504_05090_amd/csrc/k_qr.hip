@@ -111,10 +111,14 @@ size_t lds_bytes(int N) {
 // pivoted (largest remaining norm first, Businger-Golub within the panel);
 // the owners recompute their column's norm while applying each reflector,
 // and the swaps are recorded in swp[j] for the rows above the panel.
+// Reflector j is formed on the fly (x_r times its scale) where it is used
+// and stored once after the panel, so a column step needs one barrier (two
+// with pivoting); the stored values are the same products.
 template <class S, bool PIVOT>
 __device__ void panel_factor(const Lds &s, int m, int w, int *swp) {
   constexpr int LDV = S::LDV;
   const int t = threadIdx.x, sub = t & 7, qo = t >> 3;
+  double *scl = s.red;   // [w] scale of each reflector column, applied after the panel
   // pn[q]: norm^2 of column q over rows >= j; pg[q]: over rows > j
   {
     const int q = qo;
@@ -127,19 +131,21 @@ __device__ void panel_factor(const Lds &s, int m, int w, int *swp) {
     __syncthreads();
   }
   for (int j = 0; j < w; ++j) {
+    // pivot: every wavefront finds the first column of largest norm among
+    // j..w-1 (lane q holds column j + q; w <= 64).  The norms of columns
+    // > j are recomputed by their owners below, so pn / pg are not permuted:
+    // the norm of the column moved to j is read at its old position p.
+    int p = j;
     if (PIVOT) {
-      // every wavefront finds the first column of largest norm among j..w-1
-      // (lane q holds column j + q; w <= 64)
       const int lane = t & 63;
       double best = (j + lane < w) ? s.pn[j + lane] : -1.0;
-      int p = j + lane;
+      p = j + lane;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         const double ob = __shfl_xor(best, o, 64);
         const int op = __shfl_xor(p, o, 64);
         if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
       }
-      __syncthreads();   // every thread has read pn before thread 0 permutes it
       if (p != j) {
         for (int r = t; r < m; r += QT) {
           const double a = s.V[r * LDV + j];
@@ -147,15 +153,10 @@ __device__ void panel_factor(const Lds &s, int m, int w, int *swp) {
           s.V[r * LDV + p] = a;
         }
       }
-      if (t == 0) {
-        swp[j] = p;
-        const double a = s.pn[j], b = s.pg[j];
-        s.pn[j] = s.pn[p]; s.pg[j] = s.pg[p];
-        s.pn[p] = a; s.pg[p] = b;
-      }
+      if (t == 0) swp[j] = p;
       __syncthreads();
     }
-    const double xn2 = s.pg[j];
+    const double xn2 = s.pg[p];
     const double x0 = s.V[j * LDV + j];
     double tj = 0.0, bj = x0, scale = 0.0;
     if (xn2 > 0.0) {
@@ -163,21 +164,41 @@ __device__ void panel_factor(const Lds &s, int m, int w, int *swp) {
       tj = (bj - x0) / bj;
       scale = 1.0 / (x0 - bj);
     }
-    for (int r = j + 1 + t; r < m; r += QT) s.V[r * LDV + j] *= scale;
-    if (t == 0) { s.tau[j] = tj; s.beta[j] = bj; }
-    __syncthreads();
+    if (t == 0) { s.tau[j] = tj; s.beta[j] = bj; scl[j] = scale; }
     const int q = j + 1 + qo;
     double a1 = 0.0, head = 0.0;   // norms of column q over rows > j+1 and its row j+1
     if (q < w) {
+      // four rows per iteration: their loads are issued together, the sums
+      // keep the row order
       double acc = (sub == 0) ? s.V[j * LDV + q] : 0.0;
-      for (int r = j + 1 + sub; r < m; r += 8) acc += s.V[r * LDV + j] * s.V[r * LDV + q];
+      int r = j + 1 + sub;
+      for (; r + 24 < m; r += 32) {
+        double x[4], c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { x[u] = s.V[(r + 8 * u) * LDV + j] * scale; c[u] = s.V[(r + 8 * u) * LDV + q]; }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += x[u] * c[u];
+      }
+      for (; r < m; r += 8) acc += (s.V[r * LDV + j] * scale) * s.V[r * LDV + q];
       acc += __shfl_xor(acc, 1, 64);
       acc += __shfl_xor(acc, 2, 64);
       acc += __shfl_xor(acc, 4, 64);
       const double f = tj * acc;
       if (sub == 0) s.V[j * LDV + q] -= f;
-      for (int r = j + 1 + sub; r < m; r += 8) {
-        const double v = s.V[r * LDV + q] - f * s.V[r * LDV + j];
+      r = j + 1 + sub;
+      for (; r + 24 < m; r += 32) {
+        double x[4], c[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) { x[u] = s.V[(r + 8 * u) * LDV + j] * scale; c[u] = s.V[(r + 8 * u) * LDV + q]; }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double v = c[u] - f * x[u];
+          s.V[(r + 8 * u) * LDV + q] = v;
+          if (r + 8 * u > j + 1) a1 += v * v; else head = v;
+        }
+      }
+      for (; r < m; r += 8) {
+        const double v = s.V[r * LDV + q] - f * (s.V[r * LDV + j] * scale);
         s.V[r * LDV + q] = v;
         if (r > j + 1) a1 += v * v; else head = v;
       }
@@ -187,6 +208,12 @@ __device__ void panel_factor(const Lds &s, int m, int w, int *swp) {
     if (q < w && sub == 0) { s.pg[q] = a1; s.pn[q] = a1 + head * head; }
     __syncthreads();
   }
+  // store the reflectors: v_r = x_r * scale below the diagonal
+  for (int e = t; e < m * w; e += QT) {
+    const int r = e / w, jj = e % w;
+    if (r > jj) s.V[r * LDV + jj] *= scl[jj];
+  }
+  __syncthreads();
 }
 
 // Write the factored panel to global (R on and above the diagonal, v below)
@@ -586,21 +613,29 @@ __device__ void factor(const Lds &s, double *A, double *Tsave, double *scratch, 
     QR_TICK(1);
     panel_factor<S, PIVOT>(s, m, w, s.sel);
     if (PIVOT) {
-      // the in-panel swaps also permute the R rows above the panel and orig[]
-      for (int r = threadIdx.x; r < c0; r += QT)
+      // the in-panel swaps also permute the R rows above the panel and orig[]:
+      // as one gather per row, column q of the result from column idx[q]
+      int *idx = s.sel + NB;
+      if (threadIdx.x == 0) {
+        for (int q = 0; q < w; ++q) idx[q] = q;
         for (int j = 0; j < w; ++j) {
           const int p = s.sel[j];
           if (p != j) {
-            const double a = A[(long)r * N + c0 + j];
-            A[(long)r * N + c0 + j] = A[(long)r * N + c0 + p];
-            A[(long)r * N + c0 + p] = a;
+            const int a = idx[j]; idx[j] = idx[p]; idx[p] = a;
+            const int o = s.orig[c0 + j]; s.orig[c0 + j] = s.orig[c0 + p]; s.orig[c0 + p] = o;
           }
         }
-      if (threadIdx.x == 0)
-        for (int j = 0; j < w; ++j) {
-          const int p = s.sel[j];
-          if (p != j) { const int a = s.orig[c0 + j]; s.orig[c0 + j] = s.orig[c0 + p]; s.orig[c0 + p] = a; }
-        }
+      }
+      __syncthreads();
+      for (int r = threadIdx.x; r < c0; r += QT) {
+        double v[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q < w) v[q] = A[(long)r * N + c0 + idx[q]];
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+          if (q < w) A[(long)r * N + c0 + q] = v[q];
+      }
       __syncthreads();
     }
     QR_TICK(2);
