@@ -115,7 +115,7 @@ size_t lds_bytes(int N) {
 // and stored once after the panel, so a column step needs one barrier (two
 // with pivoting); the stored values are the same products.
 template <class S, bool PIVOT>
-__device__ void panel_factor(const Lds &s, int m, int w, int *swp) {
+__device__ __forceinline__ void panel_factor(const Lds &s, int m, int w, int *swp) {
   constexpr int LDV = S::LDV;
   const int t = threadIdx.x, sub = t & 7, qo = t >> 3;
   double *scl = s.red;   // [w] scale of each reflector column, applied after the panel
@@ -220,7 +220,7 @@ __device__ void panel_factor(const Lds &s, int m, int w, int *swp) {
 // and turn LDS V into the clean reflector block (1 on the diagonal, zeros
 // above and in the padding up to mr x NB).
 template <class S>
-__device__ void panel_store_clean(const Lds &s, double *A, int N, int c0, int m, int w, int mr) {
+__device__ __forceinline__ void panel_store_clean(const Lds &s, double *A, int N, int c0, int m, int w, int mr) {
   constexpr int LDV = S::LDV;
   for (int e = threadIdx.x; e < m * w; e += QT) {
     const int r = e / w, q = e % w;
@@ -236,7 +236,7 @@ __device__ void panel_store_clean(const Lds &s, double *A, int N, int c0, int m,
 }
 
 template <class S>
-__device__ void panel_load_clean(const Lds &s, const double *A, int N, int c0, int m, int w, int mr) {
+__device__ __forceinline__ void panel_load_clean(const Lds &s, const double *A, int N, int c0, int m, int w, int mr) {
   constexpr int LDV = S::LDV;
   for (int e = threadIdx.x; e < mr * S::NB; e += QT) {
     const int r = e / S::NB, q = e % S::NB;
@@ -250,7 +250,7 @@ __device__ void panel_load_clean(const Lds &s, const double *A, int N, int c0, i
 // T_jj = tau_j,  T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j).
 // The Gram matrix V^T V comes from FP64 MFMA (K split over the wavefronts).
 template <class S>
-__device__ void build_T(const Lds &s, int m, int w, int mr) {
+__device__ __forceinline__ void build_T(const Lds &s, int m, int w, int mr) {
   constexpr int LDV = S::LDV, NB = S::NB, WT = S::WT;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, l16 = lane & 15, lq = lane >> 4;
   double *part = s.Wp;                    // [4][NB][NB] partial Gram matrices
@@ -302,7 +302,7 @@ __device__ void build_T(const Lds &s, int m, int w, int mr) {
 // (Q_p, used to form Q).  With NORMS, the squared norms of the updated
 // columns over rows >= r0 + nskip are left in s.norms[col].
 template <class S, bool TRANS_T, bool NORMS>
-__device__ void apply_block(const Lds &s, double *X, long ldx, int r0, int m, int mr, int c0, int c1, int nskip) {
+__device__ __forceinline__ void apply_block(const Lds &s, double *X, long ldx, int r0, int m, int mr, int c0, int c1, int nskip) {
   constexpr int LDV = S::LDV, NB = S::NB, CW = S::CW, CT = S::CT, WT = S::WT, RTW = S::RTW;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
@@ -421,7 +421,7 @@ __device__ void apply_block(const Lds &s, double *X, long ldx, int r0, int m, in
 // wavefronts.  With NORMS each column's squared norm over rows >= nskip is
 // summed within the wavefront.
 template <class S, bool TRANS_T, bool NORMS>
-__device__ void apply_cols(const Lds &s, double *X, long ldx, int r0, int m, int mr, int c0, int c1, int nskip) {
+__device__ __forceinline__ void apply_cols(const Lds &s, double *X, long ldx, int r0, int m, int mr, int c0, int c1, int nskip) {
   constexpr int LDV = S::LDV, NB = S::NB, WT = S::WT, MT = S::MT;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
@@ -517,7 +517,7 @@ __device__ void apply_cols(const Lds &s, double *X, long ldx, int r0, int m, int
 }
 
 template <class S, bool TRANS_T, bool NORMS>
-__device__ void apply(const Lds &s, double *X, long ldx, int r0, int m, int mr, int c0, int c1, int nskip) {
+__device__ __forceinline__ void apply(const Lds &s, double *X, long ldx, int r0, int m, int mr, int c0, int c1, int nskip) {
   if constexpr (S::COLS) apply_cols<S, TRANS_T, NORMS>(s, X, ldx, r0, m, mr, c0, c1, nskip);
   else apply_block<S, TRANS_T, NORMS>(s, X, ldx, r0, m, mr, c0, c1, nskip);
 }
@@ -529,7 +529,7 @@ __device__ void apply(const Lds &s, double *X, long ldx, int r0, int m, int mr, 
 // rows above the panel stay consistent; the chosen columns are staged in the
 // (still free) panel area of LDS.
 template <class S>
-__device__ void select_panel(const Lds &s, double *A, int N, int c0, int w) {
+__device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int c0, int w) {
   constexpr int LDV = S::LDV;
   const int t = threadIdx.x;
   int *rank = s.sel;          // [N]
@@ -598,7 +598,7 @@ __device__ void select_panel(const Lds &s, double *A, int N, int c0, int w) {
 // PIVOT: panel selection by current norms (udv).  B: reflectors also applied
 // to B's nrhs columns (solve).
 template <class S, bool PIVOT>
-__device__ void factor(const Lds &s, double *A, double *Tsave, double *scratch, int N, double *B, int nrhs) {
+__device__ __forceinline__ void factor(const Lds &s, double *A, double *Tsave, double *scratch, int N, double *B, int nrhs) {
   constexpr int NB = S::NB, LDV = S::LDV;
   QR_TICK_INIT;
   for (int c0 = 0; c0 < N; c0 += NB) {
