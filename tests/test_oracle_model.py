@@ -55,6 +55,25 @@ def test_hopping_spectrum_is_tight_binding(orc, L):
     assert np.max(np.abs(ev - np.sort(dispersion(L, 0.25)))) < 1e-14
 
 
+@pytest.mark.parametrize("L", [2, 4, 6, 16])
+def test_hopping_exponential_is_a_kronecker_product(orc, L):
+    """The hopping of eq. (1) on the periodic square lattice is the sum of two
+    commuting ring hoppings, so e^{sK} = R (x) R with R = e^{-s t A} of the
+    L-site ring (A its adjacency; both bonds of the L = 2 ring join the same
+    pair of sites).  This exact factorisation is what the library's Kronecker
+    hopping option applies; here it is checked on the oracle's own K and
+    exponential against scipy's expm of the ring."""
+    t = 0.25
+    A = np.zeros((L, L))
+    for x in range(L):
+        A[x, (x + 1) % L] += 1.0
+        A[x, (x - 1) % L] += 1.0
+    K = orc.hopping(L, t)
+    for s in (-0.5, 0.5, -0.4):
+        R = sla.expm(-s * t * A)
+        assert np.max(np.abs(orc.expm(K, s) - np.kron(R, R))) < 1e-14, s
+
+
 @pytest.mark.parametrize("dtau", [0.1, 0.5, 0.8, 2.0])
 def test_expm_against_scipy(orc, dtau):
     K = orc.hopping(6, 0.25)
