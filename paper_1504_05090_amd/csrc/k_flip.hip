@@ -256,6 +256,13 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
 // value that enters G are the same in both lanes.  Twice the wavefronts also
 // double the loads in flight during a flush.
 
+// LDS strides of the paired flush: rows of -X are padded to KM + 2 (FP64) or
+// KM + 4 (FP32) elements and rows of Y^T to sites + 16, so that the MFMA
+// operand reads (16 rows or columns by 4 k values per instruction) and the
+// owners' writes touch distinct banks
+template <typename T, int KM> constexpr int pair_xld() { return KM + (sizeof(T) == 8 ? 2 : 4); }
+constexpr int PAIR_YPAD = 16;
+
 // G0 <- G0 - X Y^T for one spin with the pairs split over the two lanes of
 // each site (same MFMA scheme as flush_spin).
 template <typename T, int KM>
@@ -263,7 +270,7 @@ __device__ void flush_pairs(T *G, int N, int fb, int ldy, const T (&xs)[KM / 2],
                             T *Ys) {
   // tiles in flight per wavefront: with twice the wavefronts, 4 FP64 tiles
   // keep the register budget of 2 waves per SIMD next to the X, Y halves
-  constexpr int H = KM / 2, TB = sizeof(T) == 8 ? 4 : 8;
+  constexpr int H = KM / 2, TB = sizeof(T) == 8 ? 4 : 8, XLD = pair_xld<T, KM>();
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
   const int j = t >> 1, hf = t & 1;
   const int l16 = lane & 15, lq = lane >> 4;
@@ -276,7 +283,7 @@ __device__ void flush_pairs(T *G, int N, int fb, int ldy, const T (&xs)[KM / 2],
     __syncthreads();
     if (j >= i0 && j < i0 + fb) {
 #pragma unroll
-      for (int q = 0; q < H; ++q) Xs[(j - i0) * (KM + 1) + 2 * q + hf] = own ? -xs[q] : (T)0;
+      for (int q = 0; q < H; ++q) Xs[(j - i0) * XLD + 2 * q + hf] = own ? -xs[q] : (T)0;
     }
     __syncthreads();
     const int nrb = min(fb, N - i0);
@@ -301,7 +308,7 @@ __device__ void flush_pairs(T *G, int N, int fb, int ldy, const T (&xs)[KM / 2],
 #pragma unroll
           for (int s0 = 0; s0 < KM; s0 += 4) {
             const int s = s0 + lq;
-            const T av = Xs[(tr * 16 + l16) * (KM + 1) + s];
+            const T av = Xs[(tr * 16 + l16) * XLD + s];
             const T bv = Ys[s * ldy + tc * 16 + l16];
             acc[b] = Mfma<T>::mac(av, bv, acc[b]);
           }
@@ -323,7 +330,7 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
   constexpr int H = KM / 2;
   extern __shared__ char smem_raw[];
   T *Xs = (T *)smem_raw;                                  // [fb][KM+1]
-  T *Ys = Xs + a.fb * (KM + 1);                           // [KM][ldy]
+  T *Ys = Xs + a.fb * pair_xld<T, KM>();                  // [KM][ldy]
   __shared__ int first[2][8];
   __shared__ T bX[2][2][KM], bY[2][2][KM];
   __shared__ double bF[2][2];
@@ -333,7 +340,7 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
 
   const int N = a.N, t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
   const int j = t >> 1, hf = t & 1;
-  const int ldy = (blockDim.x >> 1) + 1;
+  const int ldy = (blockDim.x >> 1) + PAIR_YPAD;
   const int c = blockIdx.x;
   const bool own = j < N;
   const long NN = (long)N * N;
@@ -484,12 +491,13 @@ hipError_t launch_pairs(const FlipArgs &a0, hipStream_t s) {
   FlipArgs a = a0;
   const int sites = ((a.N + 31) / 32) * 32;           // 32 sites per wavefront
   const int threads = 2 * sites;
-  const size_t ybytes = sizeof(T) * (size_t)KM * (sites + 1);
+  constexpr int XLD = pair_xld<T, KM>();
+  const size_t ybytes = sizeof(T) * (size_t)KM * (sites + PAIR_YPAD);
   const size_t budget = 146 * 1024;
   int fb = 16;
-  while (fb < a.N && ybytes + sizeof(T) * (size_t)(fb + 16) * (KM + 1) <= budget) fb += 16;
+  while (fb < a.N && ybytes + sizeof(T) * (size_t)(fb + 16) * XLD <= budget) fb += 16;
   a.fb = fb;
-  const size_t lds = sizeof(T) * (size_t)fb * (KM + 1) + ybytes;
+  const size_t lds = sizeof(T) * (size_t)fb * XLD + ybytes;
   if (threads > 512) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_flip_pairs<T, KM>), dim3(a.chains), dim3(threads), lds, s, a);
   return hipGetLastError();

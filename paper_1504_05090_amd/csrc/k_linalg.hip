@@ -142,23 +142,36 @@ __global__ __launch_bounds__(QT) void k_qr_solve(double *Mall, double *Ball, int
 // M = Db_R^{-1} (U_R^T U_L) Db_L^{-1} + Ds_R (V_R V_L^T) Ds_L   (W1 in, M out)
 // or, without a left factor,  M = Db_R^{-1} U_R^T + Ds_R V_R;
 // RHS = Db_R^{-1} U_R^T.
-__global__ void k_fresh_prep(const double *UR, const double *DR, const double *VR, double *W1,
-                             const double *W2, const double *DL, double *RHS, int mats, int N) {
-  const long NN = (long)N * N;
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= NN * mats) return;
-  const long m = e / NN, r = e % NN;
-  const int i = (int)(r / N), j = (int)(r % N);
-  const double dr = DR[m * N + i];
-  const double drb = big_part(dr), drs = dr / drb;
-  const double ut = UR[m * NN + (long)j * N + i] / drb;
-  RHS[e] = ut;
-  if (DL) {
-    const double dl = DL[m * N + j];
-    const double dlb = big_part(dl), dls = dl / dlb;
-    W1[e] = W1[e] / (drb * dlb) + drs * W2[e] * dls;
-  } else {
-    W1[e] = ut + drs * VR[e];
+// One 32 x 32 tile of one matrix per workgroup (32 x 8 threads): the tile
+// of U_R^T is staged through LDS so that both its read and the outputs are
+// coalesced.
+__global__ __launch_bounds__(256) void k_fresh_prep(const double *UR, const double *DR, const double *VR,
+                                                    double *W1, const double *W2, const double *DL, double *RHS,
+                                                    int N) {
+  __shared__ double tile[32][33];
+  const long NN = (long)N * N, m = blockIdx.y;
+  const int tn = (N + 31) / 32, i0 = (blockIdx.x / tn) * 32, j0 = (blockIdx.x % tn) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {   // rows j0 + r of U_R, columns i0 + tx
+    const int jj = j0 + r, ii = i0 + tx;
+    tile[r][tx] = (jj < N && ii < N) ? UR[m * NN + (long)jj * N + ii] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + tx;
+    if (i >= N || j >= N) continue;
+    const long e = m * NN + (long)i * N + j;
+    const double dr = DR[m * N + i];
+    const double drb = big_part(dr), drs = dr / drb;
+    const double ut = tile[tx][r] / drb;   // (U_R^T)_ij = U_R[j][i]
+    RHS[e] = ut;
+    if (DL) {
+      const double dl = DL[m * N + j];
+      const double dlb = big_part(dl), dls = dl / dlb;
+      W1[e] = W1[e] / (drb * dlb) + drs * W2[e] * dls;
+    } else {
+      W1[e] = ut + drs * VR[e];
+    }
   }
 }
 
@@ -173,19 +186,20 @@ __global__ void k_time_rhs(const double *DR, const double *VR, double *RHS, int 
 
 // drift = max_ij |G_cmp - G_fresh| over both spins of one chain, then the
 // fresh matrices are written to G_out (rounded to its type).  G_cmp and G_out
-// may be the same buffer.
+// may be the same buffer.  Workgroup (p, c) takes part p of chain c and
+// leaves its maxima of |G_cmp - G_fresh|, |G_fresh| and of the non-finite
+// flag in part[c][p][0..2]; k_drift_final reduces them per chain.
 template <typename Tc, typename To>
-__global__ __launch_bounds__(256) void k_drift_replace(const Tc *Gc, To *Go, const double *Gf, int N,
-                                                       ChainStats *stats, int *err, double drift_abort,
-                                                       int count) {
+__global__ __launch_bounds__(256) void k_drift_part(const Tc *Gc, To *Go, const double *Gf, int N, double *part) {
   __shared__ double red[16];
-  const long n = 2L * N * N, c = blockIdx.x;
+  const long n = 2L * N * N, c = blockIdx.y;
+  const long len = (n + DRIFT_PARTS - 1) / DRIFT_PARTS, e0 = blockIdx.x * len, e1 = min(n, e0 + len);
   const Tc *gc = Gc + c * n;
   To *go = Go + c * n;
   const double *gf = Gf + c * n;
   double dmax = 0.0, gmax = 0.0;
   bool bad = false;
-  for (long e = threadIdx.x; e < n; e += blockDim.x) {
+  for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const double f = gf[e];
     if (!isfinite(f)) bad = true;
     dmax = fmax(dmax, fabs((double)gc[e] - f));
@@ -196,6 +210,21 @@ __global__ __launch_bounds__(256) void k_drift_replace(const Tc *Gc, To *Go, con
   const double gm = block_max(gmax, red);
   const double anybad = block_max(bad ? 1.0 : 0.0, red);
   if (threadIdx.x == 0) {
+    double *pp = part + (c * DRIFT_PARTS + blockIdx.x) * 3;
+    pp[0] = dm;
+    pp[1] = gm;
+    pp[2] = anybad;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_drift_final(const double *part, ChainStats *stats, int *err,
+                                                    double drift_abort, int count) {
+  const int c = blockIdx.x, p = threadIdx.x;
+  const double *pp = part + ((long)c * DRIFT_PARTS + p) * 3;
+  const double dm = wave_max(p < DRIFT_PARTS ? pp[0] : 0.0);
+  const double gm = wave_max(p < DRIFT_PARTS ? pp[1] : 0.0);
+  const double anybad = wave_max(p < DRIFT_PARTS ? pp[2] : 0.0);
+  if (p == 0) {
     if (count) {
       ChainStats *st = stats + c;
       const double rel = dm / fmax(1.0, gm);
@@ -231,9 +260,11 @@ hipError_t qr_solve(double *M, double *B, int mats, int N, hipStream_t s) {
 
 hipError_t fresh_prep(const double *UR, const double *DR, const double *VR, double *W1, const double *W2,
                       const double *DL, double *RHS, int mats, int N, hipStream_t s) {
-  const long n = (long)mats * N * N;
-  hipLaunchKernelGGL(k_fresh_prep, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, UR, DR, VR, W1, W2, DL,
-                     RHS, mats, N);
+  if (mats <= 0) return hipSuccess;
+  if (mats > 65535) return hipErrorInvalidValue;
+  const int tn = (N + 31) / 32;
+  hipLaunchKernelGGL(k_fresh_prep, dim3((unsigned)(tn * tn), (unsigned)mats), dim3(256), 0, s, UR, DR, VR, W1, W2,
+                     DL, RHS, N);
   return hipGetLastError();
 }
 
@@ -244,21 +275,20 @@ hipError_t time_rhs(const double *DR, const double *VR, double *RHS, int mats, i
 }
 
 hipError_t drift_replace(const void *Gc, bool cmp64, void *Go, bool out64, const double *Gf, int chains, int N,
-                         ChainStats *stats, int *err, double drift_abort, bool count, hipStream_t s) {
+                         double *part, ChainStats *stats, int *err, double drift_abort, bool count, hipStream_t s) {
+  if (chains <= 0) return hipSuccess;
+  if (chains > 65535 || !part) return hipErrorInvalidValue;
   const int cnt = count ? 1 : 0;
-  const dim3 g(chains), b(256);
+  const dim3 g(DRIFT_PARTS, chains), b(256);
   if (cmp64 && out64)
-    hipLaunchKernelGGL((k_drift_replace<double, double>), g, b, 0, s, (const double *)Gc, (double *)Go, Gf, N, stats,
-                       err, drift_abort, cnt);
+    hipLaunchKernelGGL((k_drift_part<double, double>), g, b, 0, s, (const double *)Gc, (double *)Go, Gf, N, part);
   else if (cmp64)
-    hipLaunchKernelGGL((k_drift_replace<double, float>), g, b, 0, s, (const double *)Gc, (float *)Go, Gf, N, stats,
-                       err, drift_abort, cnt);
+    hipLaunchKernelGGL((k_drift_part<double, float>), g, b, 0, s, (const double *)Gc, (float *)Go, Gf, N, part);
   else if (out64)
-    hipLaunchKernelGGL((k_drift_replace<float, double>), g, b, 0, s, (const float *)Gc, (double *)Go, Gf, N, stats,
-                       err, drift_abort, cnt);
+    hipLaunchKernelGGL((k_drift_part<float, double>), g, b, 0, s, (const float *)Gc, (double *)Go, Gf, N, part);
   else
-    hipLaunchKernelGGL((k_drift_replace<float, float>), g, b, 0, s, (const float *)Gc, (float *)Go, Gf, N, stats,
-                       err, drift_abort, cnt);
+    hipLaunchKernelGGL((k_drift_part<float, float>), g, b, 0, s, (const float *)Gc, (float *)Go, Gf, N, part);
+  hipLaunchKernelGGL(k_drift_final, dim3(chains), dim3(64), 0, s, part, stats, err, drift_abort, cnt);
   return hipGetLastError();
 }
 

@@ -105,9 +105,12 @@ hipError_t fresh_prep(const double *UR, const double *DR, const double *VR, doub
                       const double *W2, const double *DL, double *RHS, int mats, int N,
                       hipStream_t s);
 // drift = max |G_cmp - Gf| per chain; G_out <- Gf (rounded to G_out's type);
-// cmp64 / out64 select FP64 or FP32 for G_cmp / G_out
+// cmp64 / out64 select FP64 or FP32 for G_cmp / G_out.  Each chain is split
+// over DRIFT_PARTS workgroups whose maxima go to part (chains * DRIFT_PARTS * 3
+// doubles of scratch) before one wavefront per chain reduces them.
+constexpr int DRIFT_PARTS = 16;
 hipError_t drift_replace(const void *Gcmp, bool cmp64, void *Gout, bool out64, const double *Gf,
-                         int chains, int N, ChainStats *stats, int *err, double drift_abort,
+                         int chains, int N, double *part, ChainStats *stats, int *err, double drift_abort,
                          bool count, hipStream_t s);
 // dst <- src between FP64 and FP32 Green-function stacks (n elements)
 hipError_t convert_green(const void *src, bool src64, void *dst, bool dst64, long n, hipStream_t s);

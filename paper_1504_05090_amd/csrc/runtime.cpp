@@ -72,6 +72,7 @@ struct Shard {
   double *RU = nullptr, *RD = nullptr, *RV = nullptr;   // right chain after block b: [nb][...]
   double *LU = nullptr, *LD = nullptr, *LV = nullptr;   // left factors, entry b: (B_Lam..B_{l_b+1})^T
   double *W1 = nullptr, *W2 = nullptr, *W3 = nullptr, *Gf = nullptr, *Gt = nullptr, *invb = nullptr;
+  double *dpart = nullptr;               // per-workgroup drift maxima [C][DRIFT_PARTS][3]
   double *Tq = nullptr;                  // compact-WY T factors of the blocked QR
   double *Sq = nullptr;                  // column-swap scratch of the blocked QR
   ChainStats *stats = nullptr;
@@ -261,6 +262,7 @@ void layout_shard(Shard &I, bool fp64, Carver &cv) {
   I.Gf = cv.take<double>(M * NN);
   I.Gt = cv.take<double>(M * NN);
   I.invb = cv.take<double>(M * I.N);
+  I.dpart = cv.take<double>((size_t)I.C * DRIFT_PARTS * 3);
   I.Tq = cv.take<double>(M * qr_tsave_doubles(I.N));
   I.Sq = cv.take<double>(M * qr_scratch_doubles(I.N));
   I.stats = cv.take<ChainStats>(I.C);
@@ -391,7 +393,7 @@ struct Exec {
   void replace(int next, bool count, double abort_at) {
     const bool out64 = !fp32_at(next);
     Timed tm(c, F_DRIFT, s);
-    chk(drift_replace(Gcur(), I.cur64, out64 ? (void *)I.G64 : (void *)I.G32, out64, I.Gf, I.C, I.N, I.stats,
+    chk(drift_replace(Gcur(), I.cur64, out64 ? (void *)I.G64 : (void *)I.G32, out64, I.Gf, I.C, I.N, I.dpart, I.stats,
                       c->err, abort_at, count, s));
     I.cur64 = out64;
   }
