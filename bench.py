@@ -42,15 +42,17 @@ HBM_PEAK = 8.0e12
 # counters were taken on (sha1 prefix); otherwise the traffic is reported as
 # null.
 _COMMON_TRAFFIC = {
-    "flip_f64": (1.218e9, "k_flip.hip", "7e46c103ee76"),
-    "flip_f32": (5.759e8, "k_flip.hip", "7e46c103ee76"),
-    "qr_udv": (2.814e9, "k_qr.hip", "2f24f3565c6e"),
-    "qr_solve": (3.468e9, "k_qr.hip", "2f24f3565c6e"),
+    "flip_f64": (1.218e9, "k_flip.hip", "5713f290969f"),
+    "flip_f32": (5.755e8, "k_flip.hip", "5713f290969f"),
+    "qr_udv": (2.813e9, "k_qr.hip", "2f2037c9d00f"),
+    "qr_solve": (3.470e9, "k_qr.hip", "2f2037c9d00f"),
 }
 TRAFFIC = {
     "dense": dict(_COMMON_TRAFFIC, **{
-        "wrap_f32": (2.046e8, "k_gemm.hip", "b592526b28ba"),
-        "wrap_f64": (6.622e8, "k_gemm.hip", "b592526b28ba"),
+        "wrap_f32": (2.046e8, "k_gemm.hip", "6164e228b0c1"),
+        # mean over every dispatch of the FP64 NN GEMM kernel (wraps, block
+        # products and UDV products share it)
+        "wrap_f64": (6.633e8, "k_gemm.hip", "6164e228b0c1"),
     }),
     "kronecker": dict(_COMMON_TRAFFIC, **{
         # wraps: one right and one left Kronecker-factor product each (mean of the two)
