@@ -119,16 +119,23 @@ def test_recorded_trace_is_the_oracle_history():
         assert np.array_equal(tr[:, c], want)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_replayed_history_from_a_different_generator(precision):
+@pytest.mark.parametrize("precision,hopping,L,beta", [("fp64", 0, 8, 5.0), ("mixed", 0, 8, 5.0),
+                                                      ("fp64", bss.FLAG_KRONECKER_HOPPING, 8, 5.0),
+                                                      ("mixed", bss.FLAG_KRONECKER_HOPPING, 8, 5.0),
+                                                      ("mixed", bss.FLAG_KRONECKER_HOPPING, 18, 2.5)])
+def test_replayed_history_from_a_different_generator(precision, hopping, L, beta):
     """Forced history: the oracle runs a chain with another key and records
-    its decisions; the GPU replays them from the same initial field."""
-    L, U, beta, dtau, n_stab = 8, 2.0, 5.0, 0.5, 5
+    its decisions; the GPU replays them from the same initial field (also with
+    FP32 slices, whose own decisions could differ from the oracle's at the
+    margin, and with the FP32 Kronecker-factor products of both strip shapes,
+    L <= 16 and L > 16)."""
+    U, dtau, n_stab = 2.0, 0.5, 5
     f0 = random_field(L, beta, dtau, 77)
     o = oracle.Chain(L, U, T, beta, dtau, 424242, 0, 0, n_stab)
     o.set_field(f0)
     tr = o.sweep(2, record=True)
-    g = ctx(L, U, beta, dtau, 1, precision=precision, k=8, n_stab=n_stab, flags=bss.FLAG_REPLAY_TRACE, trace_sweeps=2)
+    g = ctx(L, U, beta, dtau, 1, precision=precision, k=8, n_stab=n_stab, flags=bss.FLAG_REPLAY_TRACE | hopping,
+            trace_sweeps=2)
     g.set_field(f0)
     g.set_trace(tr, 2)
     g.sweep(2)
