@@ -706,28 +706,55 @@ __global__ __launch_bounds__(QT) void k_qr_solve(double *Mall, double *Ball, dou
   factor<S, false>(s, M, Ts, nullptr, N, B, N);
   // back substitution R Z = Y (Y = Q^T B in B), block rows from the bottom
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
   const int np = (N + NB - 1) / NB;
   double *Rd = s.T;   // diagonal block of R, [NB][NB]
+  // the panel and partial-sum areas (contiguous, free after the factorisation)
+  // hold the block row of R right of the diagonal block; the row stride is
+  // 2 mod 32 doubles so that the MFMA operand reads hit distinct banks
+  double *Rs = s.V;
+  const int RLD = ((N + 31) / 32) * 32 + 2;
   for (int p = np - 1; p >= 0; --p) {
     const int r0 = p * NB, w = min(NB, N - r0), k0 = r0 + w, kn = N - k0;
     if (kn > 0) {   // Y_p -= R[r0:r0+w, k0:N] Z[k0:N, :]
+      for (int e = t; e < NB * kn; e += QT) {
+        const int i = e / kn, k = e % kn;
+        Rs[i * RLD + k] = (i < w) ? M[(long)(r0 + i) * N + k0 + k] : 0.0;
+      }
+      __syncthreads();
+      // one 16-column tile per wavefront at a time, for every row tile of the
+      // block row: each element of Z is loaded once, four k-steps ahead
       const int ctiles = (N + 15) / 16;
-      for (int tile = wv; tile < (NB / 16) * ctiles; tile += 4) {
-        const int tr = tile / ctiles, tc = tile % ctiles;
-        M64::acc_t acc = {0, 0, 0, 0};
-        const int ri = r0 + tr * 16 + (lane & 15);
-        const int cj = tc * 16 + (lane & 15);
-        for (int kk = 0; kk < kn; kk += 4) {
-          const int k = k0 + kk + (lane >> 4);
-          const double a = (ri < r0 + w && k < N) ? M[(long)ri * N + k] : 0.0;
-          const double bb = (k < N && cj < N) ? B[(long)k * N + cj] : 0.0;
-          acc = M64::mac(a, bb, acc);
+      for (int tc = wv; tc < ctiles; tc += QT / 64) {
+        const int cj = tc * 16 + l16;
+        M64::acc_t acc[S::WT];
+#pragma unroll
+        for (int tr = 0; tr < S::WT; ++tr) acc[tr] = M64::acc_t{0, 0, 0, 0};
+        int kk = 0;
+        for (; kk + 16 <= kn; kk += 16) {
+          double bz[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) bz[u] = (cj < N) ? B[(long)(k0 + kk + 4 * u + lq) * N + cj] : 0.0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int tr = 0; tr < S::WT; ++tr)
+              acc[tr] = M64::mac(Rs[(tr * 16 + l16) * RLD + kk + 4 * u + lq], bz[u], acc[tr]);
+        }
+        for (; kk < kn; kk += 4) {
+          const int k = kk + lq;
+          const double bb = (k < kn && cj < N) ? B[(long)(k0 + k) * N + cj] : 0.0;
+#pragma unroll
+          for (int tr = 0; tr < S::WT; ++tr)
+            acc[tr] = M64::mac(k < kn ? Rs[(tr * 16 + l16) * RLD + k] : 0.0, bb, acc[tr]);
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = r0 + tr * 16 + M64::row(lane, r);
-          if (row < r0 + w && cj < N) B[(long)row * N + cj] -= acc[r];
-        }
+        for (int tr = 0; tr < S::WT; ++tr)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = r0 + tr * 16 + M64::row(lane, r);
+            if (row < r0 + w && cj < N) B[(long)row * N + cj] -= acc[tr][r];
+          }
       }
     }
     for (int e = t; e < NB * NB; e += QT) {
