@@ -24,6 +24,10 @@ namespace {
 // KP = 4 words for FP32 and 2 doubles for FP64 spread the 16 rows of a
 // k-contiguous tile over all banks; 16 elements shift the 4 k-rows of an
 // m-contiguous tile by a quarter (FP32) or a half (FP64) of the 64 banks.
+// largest K whose column scale is staged whole in LDS: the library's largest
+// N for the big tiles, and 256 for the small ones (used below N = 192)
+template <int BM, int BN> constexpr int gemm_ks_max() { return (BM >= 128 || BN >= 128) ? 512 : 256; }
+
 template <typename T, bool TA, bool TB, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
   constexpr int WM = BM / 2, WN = BN / 2;          // 2 x 2 wavefronts
@@ -34,6 +38,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
   constexpr int EA = BM * BK / 256, EB = BK * BN / 256;   // elements per thread per chunk
   __shared__ T As[2][A_ROWS][A_LD];
   __shared__ T Bs[2][B_ROWS][B_LD];
+  __shared__ T Ksh[gemm_ks_max<BM, BN>()];   // A's column scale, staged once
 
   const int tilesN = (d.N + BN - 1) / BN;
   const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
@@ -60,22 +65,18 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
   };
   auto a_lds = [&](int buf, int ii, int kk) -> T & { return TA ? As[buf][kk][ii] : As[buf][ii][kk]; };
   auto b_lds = [&](int buf, int kk, int jj) -> T & { return TB ? Bs[buf][jj][kk] : Bs[buf][kk][jj]; };
-  // A's column scale is fetched beside A and applied when the chunk is
+  // A's column scale (staged in LDS once) is applied when a chunk is
   // stashed, so no fetched value is consumed before the current chunk's MFMAs
-  T ra[EA], rk[EA], rb[EB];
+  T ra[EA], rb[EB];
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       int ii, kk;
       a_index(e, ii, kk);
       const int gi = i0 + ii, gk = k0 + kk;
-      T v = 0, sk = 0;
-      if (gi < d.M && gk < d.K) {
-        v = TA ? A[(long)gk * d.lda + gi] : A[(long)gi * d.lda + gk];
-        if (ks) sk = ks[gk];
-      }
+      T v = 0;
+      if (gi < d.M && gk < d.K) v = TA ? A[(long)gk * d.lda + gi] : A[(long)gi * d.lda + gk];
       ra[e] = v;
-      rk[e] = sk;
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -87,12 +88,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
       rb[e] = v;
     }
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](int buf, int k0) {
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
       int ii, kk;
       a_index(e, ii, kk);
-      a_lds(buf, ii, kk) = ks ? ra[e] * rk[e] : ra[e];
+      const int gk = k0 + kk;
+      a_lds(buf, ii, kk) = (ks && gk < d.K) ? ra[e] * Ksh[gk] : ra[e];
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
@@ -111,7 +113,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
 
   const int nk = (d.K + BK - 1) / BK;
   fetch(0);
-  stash(0);
+  if (ks) {
+    for (int e = t; e < d.K; e += 256) Ksh[e] = ks[e];
+    __syncthreads();
+  }
+  stash(0, 0);
   __syncthreads();
   for (int kc = 0; kc < nk; ++kc) {
     const int buf = kc & 1;
@@ -128,7 +134,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
 #pragma unroll
         for (int c = 0; c < TN; ++c) acc[a][c] = Mfma<T>::mac(av[a], bv[c], acc[a][c]);
     }
-    if (kc + 1 < nk) stash(buf ^ 1);
+    if (kc + 1 < nk) stash(buf ^ 1, (kc + 1) * BK);
     __syncthreads();
   }
 
@@ -153,13 +159,15 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
 }
 
 template <typename T, int BM, int BN, int BK>
-void launch_shape(const GemmDesc &d, bool ta, bool tb, hipStream_t s) {
+hipError_t launch_shape(const GemmDesc &d, bool ta, bool tb, hipStream_t s) {
+  if (d.ks && d.K > gemm_ks_max<BM, BN>()) return hipErrorInvalidValue;
   const int tiles = ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
   dim3 grid(tiles, d.batch), block(256);
   if (!ta && !tb) hipLaunchKernelGGL((k_gemm<T, false, false, BM, BN, BK>), grid, block, 0, s, d);
   else if (ta && !tb) hipLaunchKernelGGL((k_gemm<T, true, false, BM, BN, BK>), grid, block, 0, s, d);
   else if (!ta && tb) hipLaunchKernelGGL((k_gemm<T, false, true, BM, BN, BK>), grid, block, 0, s, d);
   else hipLaunchKernelGGL((k_gemm<T, true, true, BM, BN, BK>), grid, block, 0, s, d);
+  return hipSuccess;
 }
 
 template <typename T>
@@ -169,14 +177,13 @@ hipError_t launch(const GemmDesc &d, bool ta, bool tb, hipStream_t s) {
   // tile shapes measured on the batched 256^3 products: FP32 128 x 128 with
   // 32-deep K chunks, FP64 64 x 128 with 16-deep chunks (fewer registers)
   const bool big = d.M >= 192 && d.N >= 192;
+  hipError_t e;
   if constexpr (sizeof(T) == 4) {
-    if (big) launch_shape<T, 128, 128, 32>(d, ta, tb, s);
-    else launch_shape<T, 64, 64, 32>(d, ta, tb, s);
+    e = big ? launch_shape<T, 128, 128, 32>(d, ta, tb, s) : launch_shape<T, 64, 64, 32>(d, ta, tb, s);
   } else {
-    if (big) launch_shape<T, 64, 128, 16>(d, ta, tb, s);
-    else launch_shape<T, 64, 64, 16>(d, ta, tb, s);
+    e = big ? launch_shape<T, 64, 128, 16>(d, ta, tb, s) : launch_shape<T, 64, 64, 16>(d, ta, tb, s);
   }
-  return hipGetLastError();
+  return e != hipSuccess ? e : hipGetLastError();
 }
 }  // namespace
 
