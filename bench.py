@@ -42,23 +42,24 @@ HBM_PEAK = 8.0e12
 # counters were taken on (sha1 prefix); otherwise the traffic is reported as
 # null.
 _COMMON_TRAFFIC = {
-    "flip_f64": (1.218e9, "k_flip.hip", "5713f290969f"),
-    "flip_f32": (5.755e8, "k_flip.hip", "5713f290969f"),
-    "qr_udv": (2.813e9, "k_qr.hip", "2f2037c9d00f"),
-    "qr_solve": (3.470e9, "k_qr.hip", "2f2037c9d00f"),
+    "flip_f64": (1.162e9, "k_flip.hip", "5713f290969f"),
+    "flip_f32": (5.512e8, "k_flip.hip", "5713f290969f"),
+    "qr_udv": (2.818e9, "k_qr.hip", "b420df2d0ecd"),
+    "qr_solve": (2.952e9, "k_qr.hip", "b420df2d0ecd"),
 }
+# per launch of all 128 chains (the profile pass runs them as one shard)
 TRAFFIC = {
     "dense": dict(_COMMON_TRAFFIC, **{
-        "wrap_f32": (2.046e8, "k_gemm.hip", "6164e228b0c1"),
-        # mean over every dispatch of the FP64 NN GEMM kernel (wraps, block
-        # products and UDV products share it)
-        "wrap_f64": (6.633e8, "k_gemm.hip", "6164e228b0c1"),
+        "wrap_f32": (2.047e8, "k_gemm.hip", "acc9d743c719"),
+        # mean over every full-size dispatch of the FP64 NN GEMM kernel (wraps,
+        # block products and UDV products share it)
+        "wrap_f64": (6.588e8, "k_gemm.hip", "acc9d743c719"),
     }),
     "kronecker": dict(_COMMON_TRAFFIC, **{
         # wraps: one right and one left Kronecker-factor product each (mean of the two)
-        "wrap_f64": (2.726e8, "k_hop.hip", "990a600b01dc"),
+        "wrap_f64": (2.725e8, "k_hop.hip", "990a600b01dc"),
         "wrap_f32": (1.358e8, "k_hop.hip", "990a600b01dc"),
-        "hop_f64": (2.711e8, "k_hop.hip", "990a600b01dc"),
+        "hop_f64": (2.710e8, "k_hop.hip", "990a600b01dc"),
     }),
 }
 
@@ -261,31 +262,46 @@ def main():
             del ctxk
         print(f"[bench] Kronecker hopping: {kron}", file=sys.stderr, flush=True)
 
-    # per-kernel-family HIP-event timings of the headline path
+    # per-kernel-family HIP-event timings of the headline path, with the
+    # chains in one shard: with several shards their launches overlap, and an
+    # event pair would time other shards' work as well
     psteps = max(2, args.steps // 2)
-    ctxp, msp, stp, prof = run_path(bss, inst, "mixed", k, n_stab, psteps, 2, profile=True, flags=hflags)
+    saved = os.environ.get("BSS_SHARDS")
+    os.environ["BSS_SHARDS"] = "1"
+    try:
+        ctxp, msp, stp, prof = run_path(bss, inst, "mixed", k, n_stab, psteps, 2, profile=True, flags=hflags)
+    finally:
+        if saved is None:
+            del os.environ["BSS_SHARDS"]
+        else:
+            os.environ["BSS_SHARDS"] = saved
     del ctxp
     acc = stp["accepted"] / max(1, stp["proposals"])
-    mats = 2 * C
+    # the chains are split into shards with launches of their own: a launch
+    # covers one shard's matrices
+    shards = max(1, stp["shards"])
+    Cl = C / shards
+    mats = 2 * Cl
     fams = sorted(((f, v) for f, v in prof.items() if v[0] > 0), key=lambda kv: -kv[1][1])
     bound_time = 0.0
     for fam, (launches, tot) in fams:
-        amount, pk, _ = family_model(fam, N, mats, C, acc, k, kron_head)
+        amount, pk, _ = family_model(fam, N, mats, Cl, acc, k, kron_head)
         if amount:
             bound_time += amount * launches / pk
     dom, (launches, tot) = fams[0]
     avg_ms = tot / max(1, launches)
-    amount, peak, bound = family_model(dom, N, mats, C, acc, k, kron_head)
+    amount, peak, bound = family_model(dom, N, mats, Cl, acc, k, kron_head)
     achieved = amount / (avg_ms / 1e3) if amount else None
     scale = 1e9 if bound == "hbm" else 1e12
     roofline = {"kernel": dom, "bound": bound, "achieved": achieved / scale if achieved else None,
                 "peak": peak / scale if peak else None, "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
                 "frac": (achieved / peak) if (achieved and peak) else None, "traffic": traffic_of(dom, args.hopping),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "avg_launch_ms": avg_ms, "launches": launches,
+                "avg_launch_ms": avg_ms, "launches": launches, "shards": shards,
+                "matrices_per_launch": mats,
                 "bound_time_fraction_of_sweep": bound_time / (msp / 1e3),
                 "breakdown_ms_per_step": {kf: round(v[1] / psteps, 3) for kf, v in fams},
-                "families": {kf: _family_roofline(kf, v, N, mats, C, acc, k, kron_head) for kf, v in fams}}
+                "families": {kf: _family_roofline(kf, v, N, mats, Cl, acc, k, kron_head) for kf, v in fams}}
     print(f"[bench] profile ({msp / psteps:.2f} ms/step): {roofline['breakdown_ms_per_step']}", file=sys.stderr,
           flush=True)
 
@@ -324,7 +340,7 @@ def main():
                                + ("e^{-+dtau K} through its Kronecker factors" if kron_head
                                   else "wraps and block products as dense MFMA GEMMs"),
                    "L": p["L"], "chains": C, "beta": p["beta"], "dtau": p["dtau"], "U": p["U"], "k": k,
-                   "n_stab": n_stab, "fp32_slices": m32, "hopping": args.hopping},
+                   "n_stab": n_stab, "fp32_slices": m32, "hopping": args.hopping, "shards": st["shards"]},
         "drift_rel_max": mixed["drift_rel_max"], "drift_rel_mean": mixed["drift_rel_mean"],
         "max_dG_vs_oracle_sweep_end": max_dg, "acceptance": mixed["acceptance"],
         "fp64_path": fp64, "speedup_vs_fp64": (value / fp64_value) if fp64_value else None,

@@ -137,6 +137,8 @@ typedef struct {
   double drift_rel_max;  /* drift over max(1, max_ij |G_fresh|), per recomputation */
   double drift_rel_mean;
   int32_t sweep_graph;   /* 1 once bss_sweep replays a captured hipGraph          */
+  int32_t shards;        /* chain groups the instance is split into, each on its
+                            own streams (every kernel launch covers one group)  */
 } bss_stats;
 
 /* Per-kernel launch timing collected under BSS_FLAG_PROFILE. */

@@ -48,7 +48,7 @@ class Stats(ctypes.Structure):
                 ("sign", ctypes.c_int32), ("n_chains", ctypes.c_int32), ("N", ctypes.c_int32),
                 ("Lambda", ctypes.c_int32), ("delay_k", ctypes.c_int32), ("n_stab", ctypes.c_int32),
                 ("fp32_slices", ctypes.c_int32), ("drift_rel_max", ctypes.c_double),
-                ("drift_rel_mean", ctypes.c_double), ("sweep_graph", ctypes.c_int32)]
+                ("drift_rel_mean", ctypes.c_double), ("sweep_graph", ctypes.c_int32), ("shards", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):

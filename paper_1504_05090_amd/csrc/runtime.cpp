@@ -221,12 +221,15 @@ int auto_fp32_slices(double lambda, int n_stab) {
   return std::max(0, std::min(s, n_stab));
 }
 
-// Shards per instance: one by default -- two shards of the 16 x 16, 128-chain
-// sweep measured within 2% of one, since the GEMMs and QRs of one shard
-// already fill the chip (the environment variable BSS_SHARDS = 1..8
-// overrides, for tuning).
-int shard_count(int C) {
-  int s = 1;
+// Shards per instance.  A context of one instance splits its chains into up
+// to four shards of at least 32 chains, each on its own streams: the flip
+// kernel of a shard fills only as many CUs as it has chains and the QRs are
+// latency-bound, so the shards' launches overlap (the 16 x 16, 128-chain
+// sweep: 83.1 ms with one shard, 80.9 with two, 79.9 with four).  A batch of
+// several instances already overlaps its instances and keeps one shard each.
+// The environment variable BSS_SHARDS = 1..8 overrides, for tuning.
+int shard_count(int C, int n_instances) {
+  int s = n_instances == 1 ? std::min(4, C / 32) : 1;
   if (const char *env = std::getenv("BSS_SHARDS")) {
     const int v = std::atoi(env);
     if (v >= 1 && v <= 8) s = v;
@@ -303,7 +306,7 @@ bool resolve(const bss_instance *in, int n, const bss_options &opt, std::vector<
     UInst U;
     U.first = (int)out.size();
     U.C = I.Ctot; U.N = I.N; U.Lam = I.Lam;
-    U.count = shard_count(I.Ctot);
+    U.count = shard_count(I.Ctot, n);
     int c0 = 0;
     for (int s = 0; s < U.count; ++s) {
       Shard J = I;
@@ -1131,6 +1134,7 @@ bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
   out->drift_rel_mean = dcnt ? rsum / dcnt : 0.0;
   out->sweep_graph = c->sweep_graph[0] ? 1 : 0;
   out->n_chains = U->C;
+  out->shards = U->count;
   return BSS_OK;
 }
 
