@@ -173,8 +173,9 @@ def main():
                          "known size, to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the chains are independent Markov chains and this build has "
-              "no multi-GPU path (the sharding plan is in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the chains are independent Markov chains, which would be split "
+              "by chain range over GPUs with no exchange during sweeps, but no multi-GPU path is built; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import paper_1504_05090_amd as bss

@@ -58,7 +58,7 @@ extern "C" {
 typedef enum {
   BSS_OK = 0,
   BSS_E_INVALID_ARG = 1,   /* argument out of range or inconsistent             */
-  BSS_E_UNSUPPORTED = 2,   /* valid physics this build does not run (odd L ...)  */
+  BSS_E_UNSUPPORTED = 2,   /* valid physics the library does not run (odd L ...) */
   BSS_E_OUT_OF_MEMORY = 3, /* device allocation failed or workspace too small    */
   BSS_E_DEVICE = 4,        /* HIP runtime error                                  */
   BSS_E_NUMERICAL = 5,     /* non-finite / non-positive ratio, drift above limit */
