@@ -18,6 +18,8 @@
 //   x = (Delta/R)(e_i - c),    y = r,
 // and every d_j drops by x_j y_j.  When k pairs are stored (and at the end of
 // the slice) they are flushed into G0 by a rank-k MFMA product.
+#include <utility>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -263,16 +265,67 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
 template <typename T, int KM> constexpr int pair_xld() { return KM + (sizeof(T) == 8 ? 2 : 4); }
 constexpr int PAIR_YPAD = 16;
 
+// Lane layout.  FP32: the two halves of a site sit in adjacent lanes and the
+// accepted site's vectors are read from LDS by every lane.  FP64: the halves
+// sit in alternate rows of 16 lanes (rows 0 and 2 hold half 0 of 16
+// consecutive sites, rows 1 and 3 half 1 of the same sites), so all lanes of
+// a row need the same elements of the accepted site's vectors: each lane
+// reads one of them and a DPP row broadcast hands them round, which moves a
+// sixteenth of the LDS data of a broadcast read.
+template <typename T> struct PairLanes {
+  static constexpr bool rows = false;
+  static constexpr unsigned long long half0 = 0x5555555555555555ull;   // lanes of half 0
+  static __device__ __forceinline__ int site(int t) { return t >> 1; }
+  static __device__ __forceinline__ int half(int t) { return t & 1; }
+  static __device__ __forceinline__ int site_in_wave(int lane) { return lane >> 1; }
+  // value held by the other lane of the site (lane ^ 1): DPP quad permutation
+  // [1, 0, 3, 2] on the vector ALU
+  static __device__ __forceinline__ float partner(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+  }
+};
+template <> struct PairLanes<double> {
+  static constexpr bool rows = true;
+  static constexpr unsigned long long half0 = 0x0000FFFF0000FFFFull;
+  static __device__ __forceinline__ int site(int t) { return (t >> 6) * 32 + ((t >> 5) & 1) * 16 + (t & 15); }
+  static __device__ __forceinline__ int half(int t) { return (t >> 4) & 1; }
+  static __device__ __forceinline__ int site_in_wave(int lane) { return (lane >> 5) * 16 + (lane & 15); }
+  // value held by the other lane of the site (lane ^ 16): swizzle swapping
+  // the two rows of each 32-lane half
+  static __device__ __forceinline__ double partner(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffll), 0x401F);
+    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+  }
+};
+
+// value of lane Q of this lane's row of 16 (DPP row_newbcast); every lane of
+// the wavefront must be active
+template <int Q> __device__ __forceinline__ double row_bcast(double v) {
+  return __longlong_as_double(__builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x150 + Q, 0xF, 0xF, false));
+}
+// sum over q of x[q] * (element q of the row's vector v), accumulated in q order
+template <int H, int... Q>
+__device__ __forceinline__ double row_dot(const double (&x)[H], double v, std::integer_sequence<int, Q...>) {
+  double s = 0.0;
+  ((s += x[Q] * row_bcast<Q>(v)), ...);
+  return s;
+}
+
 // G0 <- G0 - X Y^T for one spin with the pairs split over the two lanes of
 // each site (same MFMA scheme as flush_spin).
 template <typename T, int KM>
 __device__ void flush_pairs(T *G, int N, int fb, int ldy, const T (&xs)[KM / 2], const T (&ys)[KM / 2], T *Xs,
                             T *Ys) {
-  // tiles in flight per wavefront: with twice the wavefronts, 4 FP64 tiles
+  // tiles per wavefront: two batches of TP tiles alternate, the next batch's
+  // G tiles loading while the current batch runs its MFMAs (with FP64 MFMA
+  // at a quarter of a 16x16x4 block per 16 cycles, the flush is bound by the
+  // matrix core once the loads are hidden); 2 x 2 FP64 or 2 x 4 FP32 tiles
   // keep the register budget of 2 waves per SIMD next to the X, Y halves
-  constexpr int H = KM / 2, TB = sizeof(T) == 8 ? 4 : 8, XLD = pair_xld<T, KM>();
+  constexpr int H = KM / 2, TP = sizeof(T) == 8 ? 2 : 4, XLD = pair_xld<T, KM>();
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
-  const int j = t >> 1, hf = t & 1;
+  const int j = PairLanes<T>::site(t), hf = PairLanes<T>::half(t);
   const int l16 = lane & 15, lq = lane >> 4;
   const bool own = j < N;
 #pragma unroll
@@ -288,37 +341,66 @@ __device__ void flush_pairs(T *G, int N, int fb, int ldy, const T (&xs)[KM / 2],
     __syncthreads();
     const int nrb = min(fb, N - i0);
     const int ntiles = ((nrb + 15) >> 4) * ctiles;
-    for (int base = w; base < ntiles; base += nw * TB) {
-      acc_t acc[TB];
+    // tiles base + nw * b of a batch; elements outside the block (and tiles
+    // past ntiles) read a clamped in-range address and keep zero, so every
+    // lane issues its loads unconditionally and the wait before a batch's
+    // MFMAs leaves the next batch's loads in flight
+    auto load = [&](acc_t (&acc)[TP], int base) {
 #pragma unroll
-      for (int b = 0; b < TB; ++b) {
+      for (int b = 0; b < TP; ++b) {
         const int tile = base + nw * b;
         const int tr = tile / ctiles, tc = tile % ctiles;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = i0 + tr * 16 + Mfma<T>::row(lane, r), col = tc * 16 + l16;
-          acc[b][r] = (tile < ntiles && row < i0 + nrb && col < N) ? G[(long)row * N + col] : (T)0;
+          const bool in = tile < ntiles && row < i0 + nrb && col < N;
+          const T v = G[(unsigned)(min(row, N - 1) * N + min(col, N - 1))];
+          acc[b][r] = in ? v : (T)0;
         }
       }
+    };
+    // the batch's tiles advance together through k, so each round of LDS
+    // operand reads feeds TP independent MFMAs; a tile past ntiles reads the
+    // operands of the last tile and is not stored
+    auto run = [&](acc_t (&acc)[TP], int base) {
+      int tr[TP], tc[TP];
 #pragma unroll
-      for (int b = 0; b < TB; ++b) {
-        const int tile = base + nw * b;
-        if (tile < ntiles) {
-          const int tr = tile / ctiles, tc = tile % ctiles;
+      for (int b = 0; b < TP; ++b) {
+        const int tile = min(base + nw * b, ntiles - 1);
+        tr[b] = tile / ctiles;
+        tc[b] = tile % ctiles;
+      }
 #pragma unroll
-          for (int s0 = 0; s0 < KM; s0 += 4) {
-            const int s = s0 + lq;
-            const T av = Xs[(tr * 16 + l16) * XLD + s];
-            const T bv = Ys[s * ldy + tc * 16 + l16];
-            acc[b] = Mfma<T>::mac(av, bv, acc[b]);
-          }
+      for (int s0 = 0; s0 < KM; s0 += 4) {
+        const int s = s0 + lq;
+        T av[TP], bv[TP];
+#pragma unroll
+        for (int b = 0; b < TP; ++b) {
+          av[b] = Xs[(tr[b] * 16 + l16) * XLD + s];
+          bv[b] = Ys[s * ldy + tc[b] * 16 + l16];
+        }
+#pragma unroll
+        for (int b = 0; b < TP; ++b) acc[b] = Mfma<T>::mac(av[b], bv[b], acc[b]);
+      }
+#pragma unroll
+      for (int b = 0; b < TP; ++b) {
+        if (base + nw * b < ntiles) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int row = i0 + tr * 16 + Mfma<T>::row(lane, r), col = tc * 16 + l16;
-            if (row < i0 + nrb && col < N) G[(long)row * N + col] = acc[b][r];
+            const int row = i0 + tr[b] * 16 + Mfma<T>::row(lane, r), col = tc[b] * 16 + l16;
+            if (row < i0 + nrb && col < N) G[(unsigned)(row * N + col)] = acc[b][r];
           }
         }
       }
+    };
+    const int step = nw * TP;
+    acc_t a0[TP], a1[TP];
+    load(a0, w);
+    for (int base = w; base < ntiles; base += 2 * step) {
+      load(a1, base + step);
+      run(a0, base);
+      load(a0, base + 2 * step);
+      run(a1, base + step);
     }
   }
   __syncthreads();
@@ -339,7 +421,8 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
   __shared__ int s_acc;
 
   const int N = a.N, t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
-  const int j = t >> 1, hf = t & 1;
+  typedef PairLanes<T> PL;
+  const int j = PL::site(t), hf = PL::half(t);
   const int ldy = (blockDim.x >> 1) + PAIR_YPAD;
   const int c = blockIdx.x;
   const bool own = j < N;
@@ -384,9 +467,9 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
       const double R = (1.0 + (1.0 - d[0]) * du) * (1.0 + (1.0 - d[1]) * dd);
       acc = (a.trace_mode == 2) ? forced : (uj < R);
     }
-    // both lanes of a site decide alike: look at the even lanes
-    const unsigned long long bal = __ballot(acc) & 0x5555555555555555ull;
-    if (lane == 0) first[par][w] = bal ? (w * 32 + ((__ffsll((long long)bal) - 1) >> 1)) : 0x7fffffff;
+    // both lanes of a site decide alike: look at the lanes of half 0
+    const unsigned long long bal = __ballot(acc) & PL::half0;
+    if (lane == 0) first[par][w] = bal ? (w * 32 + PL::site_in_wave(__ffsll((long long)bal) - 1)) : 0x7fffffff;
     __syncthreads();
     int ist = 0x7fffffff;
     for (int q = 0; q < nw; ++q) ist = min(ist, first[par][q]);
@@ -420,25 +503,50 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
     }
     __syncthreads();
     const int slot = m >> 1, mine_half = m & 1;
+    // the four dot products (column and row, both spins) run as independent
+    // chains over this lane's half of the pairs, in pair order, then the two
+    // halves meet
+    T pc[2] = {(T)0, (T)0}, pr[2] = {(T)0, (T)0};
+    if constexpr (PL::rows) {
+      const int e = hf * H + min(lane & 15, H - 1);
 #pragma unroll
-    for (int sp = 0; sp < 2; ++sp) {
-      T pc = (T)0, pr = (T)0;
+      for (int sp = 0; sp < 2; ++sp) {
+        const T vy = bY[par][sp][e], vx = bX[par][sp][e];
+        pc[sp] = row_dot(xs[sp], vy, std::make_integer_sequence<int, H>());
+        pr[sp] = row_dot(ys[sp], vx, std::make_integer_sequence<int, H>());
+      }
+    } else {
 #pragma unroll
       for (int q = 0; q < H; ++q) {
-        pc += xs[sp][q] * bY[par][sp][hf * H + q];
-        pr += bX[par][sp][hf * H + q] * ys[sp][q];
-      }
-      pc += __shfl_xor(pc, 1, 64);
-      pr += __shfl_xor(pr, 1, 64);
-      const T cv = gc[sp] - pc, rv = gr[sp] - pr;
-      const T xn = own ? (T)bF[par][sp] * ((j == ist ? (T)1 : (T)0) - cv) : (T)0;
-      const T yn = own ? rv : (T)0;
-      if (hf == mine_half) {
 #pragma unroll
-        for (int q = 0; q < H; ++q)
-          if (q == slot) { xs[sp][q] = xn; ys[sp][q] = yn; }
+        for (int sp = 0; sp < 2; ++sp) {
+          pc[sp] += xs[sp][q] * bY[par][sp][hf * H + q];
+          pr[sp] += bX[par][sp][hf * H + q] * ys[sp][q];
+        }
       }
-      d[sp] -= (double)xn * (double)yn;
+    }
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      pc[sp] += PL::partner(pc[sp]);
+      pr[sp] += PL::partner(pr[sp]);
+    }
+    T xn[2], yn[2];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp) {
+      const T cv = gc[sp] - pc[sp], rv = gr[sp] - pr[sp];
+      xn[sp] = own ? (T)bF[par][sp] * ((j == ist ? (T)1 : (T)0) - cv) : (T)0;
+      yn[sp] = own ? rv : (T)0;
+      d[sp] -= (double)xn[sp] * (double)yn[sp];
+    }
+    // store the pair in its slot: a branch on the block-uniform slot, so only
+    // that slot's registers are written
+    const bool keep = hf == mine_half;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      if (q == slot) {
+        asm volatile("" ::: "memory");
+        if (keep) { xs[0][q] = xn[0]; ys[0][q] = yn[0]; xs[1][q] = xn[1]; ys[1][q] = yn[1]; }
+      }
     }
     ++m;
     pos = ist + 1;
