@@ -265,52 +265,65 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
 template <typename T, int KM> constexpr int pair_xld() { return KM + (sizeof(T) == 8 ? 2 : 4); }
 constexpr int PAIR_YPAD = 16;
 
-// Lane layout.  FP32: the two halves of a site sit in adjacent lanes and the
-// accepted site's vectors are read from LDS by every lane.  FP64: the halves
-// sit in alternate rows of 16 lanes (rows 0 and 2 hold half 0 of 16
-// consecutive sites, rows 1 and 3 half 1 of the same sites), so all lanes of
-// a row need the same elements of the accepted site's vectors: each lane
-// reads one of them and a DPP row broadcast hands them round, which moves a
-// sixteenth of the LDS data of a broadcast read.
-template <typename T> struct PairLanes {
-  static constexpr bool rows = false;
-  static constexpr unsigned long long half0 = 0x5555555555555555ull;   // lanes of half 0
-  static __device__ __forceinline__ int site(int t) { return t >> 1; }
-  static __device__ __forceinline__ int half(int t) { return t & 1; }
-  static __device__ __forceinline__ int site_in_wave(int lane) { return lane >> 1; }
-  // value held by the other lane of the site (lane ^ 1): DPP quad permutation
-  // [1, 0, 3, 2] on the vector ALU
-  static __device__ __forceinline__ float partner(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
-  }
-};
-template <> struct PairLanes<double> {
-  static constexpr bool rows = true;
-  static constexpr unsigned long long half0 = 0x0000FFFF0000FFFFull;
+// Lane layout: the halves of a site sit in alternate rows of 16 lanes (rows 0
+// and 2 hold half 0 of 16 consecutive sites, rows 1 and 3 half 1 of the same
+// sites), so all lanes of a row need the same elements of the accepted site's
+// vectors: each lane reads one of them from LDS and the dot products take
+// them by DPP row broadcast, a sixteenth of the LDS data of a broadcast read.
+struct PairLanes {
+  static constexpr unsigned long long half0 = 0x0000FFFF0000FFFFull;   // lanes of half 0
   static __device__ __forceinline__ int site(int t) { return (t >> 6) * 32 + ((t >> 5) & 1) * 16 + (t & 15); }
   static __device__ __forceinline__ int half(int t) { return (t >> 4) & 1; }
   static __device__ __forceinline__ int site_in_wave(int lane) { return (lane >> 5) * 16 + (lane & 15); }
-  // value held by the other lane of the site (lane ^ 16): swizzle swapping
-  // the two rows of each 32-lane half
-  static __device__ __forceinline__ double partner(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffll), 0x401F);
-    const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
-    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-  }
 };
 
-// value of lane Q of this lane's row of 16 (DPP row_newbcast); every lane of
-// the wavefront must be active
-template <int Q> __device__ __forceinline__ double row_bcast(double v) {
-  return __longlong_as_double(__builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x150 + Q, 0xF, 0xF, false));
+// value held by the other lane of the site (lane ^ 16): swizzle swapping the
+// two rows of each 32-lane half
+__device__ __forceinline__ float pair_partner(float v) {
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
 }
-// sum over q of x[q] * (element q of the row's vector v), accumulated in q order
-template <int H, int... Q>
-__device__ __forceinline__ double row_dot(const double (&x)[H], double v, std::integer_sequence<int, Q...>) {
-  double s = 0.0;
-  ((s += x[Q] * row_bcast<Q>(v)), ...);
-  return s;
+__device__ __forceinline__ double pair_partner(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffll), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// One step q of the four dot products of an acceptance (column and row, both
+// spins): acc += (lane q of the row's v) * x, with the broadcast taken by the
+// FMA itself (DPP row_newbcast on its first source).  Inline assembly because
+// the compiler emits a separate DPP move per broadcast; the leading s_nop
+// gives the two wait states a DPP read needs after a vector-ALU write, and
+// each accumulator is written once per step, three instructions before the
+// next step reads it.  Every lane of the wavefront must be active.
+template <int Q>
+__device__ __forceinline__ void row_fmac4(double &c0, double &c1, double &r0, double &r1, double vy0, double vy1,
+                                          double vx0, double vx1, double x0, double x1, double y0, double y1) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %4, %8 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %5, %9 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %6, %10 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %7, %11 row_newbcast:%c12 row_mask:0xf bank_mask:0xf"
+      : "+v"(c0), "+v"(c1), "+v"(r0), "+v"(r1)
+      : "v"(vy0), "v"(vy1), "v"(vx0), "v"(vx1), "v"(x0), "v"(x1), "v"(y0), "v"(y1), "n"(Q));
+}
+template <int Q>
+__device__ __forceinline__ void row_fmac4(float &c0, float &c1, float &r0, float &r1, float vy0, float vy1, float vx0,
+                                          float vx1, float x0, float x1, float y0, float y1) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %4, %8 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %1, %5, %9 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %2, %6, %10 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f32_dpp %3, %7, %11 row_newbcast:%c12 row_mask:0xf bank_mask:0xf"
+      : "+v"(c0), "+v"(c1), "+v"(r0), "+v"(r1)
+      : "v"(vy0), "v"(vy1), "v"(vx0), "v"(vx1), "v"(x0), "v"(x1), "v"(y0), "v"(y1), "n"(Q));
+}
+// c_s = sum_q xs_s[q] vy_s[q], r_s = sum_q vx_s[q] ys_s[q] (s = both spins),
+// accumulated in q order, with vy_s[q], vx_s[q] held by lane q of the row
+template <typename T, int H, int... Q>
+__device__ __forceinline__ void row_dots(T (&c)[2], T (&r)[2], const T (&vy)[2], const T (&vx)[2], const T (&x)[2][H],
+                                         const T (&y)[2][H], std::integer_sequence<int, Q...>) {
+  (row_fmac4<Q>(c[0], c[1], r[0], r[1], vy[0], vy[1], vx[0], vx[1], x[0][Q], x[1][Q], y[0][Q], y[1][Q]), ...);
 }
 
 // G0 <- G0 - X Y^T for one spin with the pairs split over the two lanes of
@@ -325,7 +338,7 @@ __device__ void flush_pairs(T *G, int N, int fb, int ldy, const T (&xs)[KM / 2],
   // keep the register budget of 2 waves per SIMD next to the X, Y halves
   constexpr int H = KM / 2, TP = sizeof(T) == 8 ? 2 : 4, XLD = pair_xld<T, KM>();
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
-  const int j = PairLanes<T>::site(t), hf = PairLanes<T>::half(t);
+  const int j = PairLanes::site(t), hf = PairLanes::half(t);
   const int l16 = lane & 15, lq = lane >> 4;
   const bool own = j < N;
 #pragma unroll
@@ -421,7 +434,7 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
   __shared__ int s_acc;
 
   const int N = a.N, t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
-  typedef PairLanes<T> PL;
+  typedef PairLanes PL;
   const int j = PL::site(t), hf = PL::half(t);
   const int ldy = (blockDim.x >> 1) + PAIR_YPAD;
   const int c = blockIdx.x;
@@ -507,28 +520,15 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
     // chains over this lane's half of the pairs, in pair order, then the two
     // halves meet
     T pc[2] = {(T)0, (T)0}, pr[2] = {(T)0, (T)0};
-    if constexpr (PL::rows) {
+    {
       const int e = hf * H + min(lane & 15, H - 1);
-#pragma unroll
-      for (int sp = 0; sp < 2; ++sp) {
-        const T vy = bY[par][sp][e], vx = bX[par][sp][e];
-        pc[sp] = row_dot(xs[sp], vy, std::make_integer_sequence<int, H>());
-        pr[sp] = row_dot(ys[sp], vx, std::make_integer_sequence<int, H>());
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < H; ++q) {
-#pragma unroll
-        for (int sp = 0; sp < 2; ++sp) {
-          pc[sp] += xs[sp][q] * bY[par][sp][hf * H + q];
-          pr[sp] += bX[par][sp][hf * H + q] * ys[sp][q];
-        }
-      }
+      const T vy[2] = {bY[par][0][e], bY[par][1][e]}, vx[2] = {bX[par][0][e], bX[par][1][e]};
+      row_dots(pc, pr, vy, vx, xs, ys, std::make_integer_sequence<int, H>());
     }
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp) {
-      pc[sp] += PL::partner(pc[sp]);
-      pr[sp] += PL::partner(pr[sp]);
+      pc[sp] += pair_partner(pc[sp]);
+      pr[sp] += pair_partner(pr[sp]);
     }
     T xn[2], yn[2];
 #pragma unroll
