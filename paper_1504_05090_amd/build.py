@@ -24,10 +24,17 @@ FLAGS = [
 ]
 
 
+# per-source flags.  The GEMM keeps its MFMA accumulators in ordinary VGPRs:
+# with AGPR accumulators the compiler copies every loop-carried accumulator
+# tile from VGPRs to AGPRs and back on each trip of the K loop.  (The QR
+# kernels measure slower in that form and keep the default.)
+EXTRA = {"k_gemm.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

@@ -174,14 +174,14 @@ template <typename T>
 hipError_t launch(const GemmDesc &d, bool ta, bool tb, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.batch <= 0) return hipSuccess;
   if (d.batch > 65535) return hipErrorInvalidValue;
-  // tile shapes measured on the batched 256^3 products: FP32 128 x 128 with
-  // 32-deep K chunks, FP64 64 x 128 with 16-deep chunks (fewer registers)
+  // tile shapes measured on the batched 256^3 products: FP32 128 x 256 with
+  // 16-deep K chunks, FP64 128 x 128 with 8-deep chunks
   const bool big = d.M >= 192 && d.N >= 192;
   hipError_t e;
   if constexpr (sizeof(T) == 4) {
-    e = big ? launch_shape<T, 128, 128, 32>(d, ta, tb, s) : launch_shape<T, 64, 64, 32>(d, ta, tb, s);
+    e = big ? launch_shape<T, 128, 256, 16>(d, ta, tb, s) : launch_shape<T, 64, 64, 32>(d, ta, tb, s);
   } else {
-    e = big ? launch_shape<T, 64, 128, 16>(d, ta, tb, s) : launch_shape<T, 64, 64, 16>(d, ta, tb, s);
+    e = big ? launch_shape<T, 128, 128, 8>(d, ta, tb, s) : launch_shape<T, 64, 64, 16>(d, ta, tb, s);
   }
   return e != hipSuccess ? e : hipGetLastError();
 }
