@@ -42,18 +42,18 @@ HBM_PEAK = 8.0e12
 # counters were taken on (sha1 prefix); otherwise the traffic is reported as
 # null.
 _COMMON_TRAFFIC = {
-    "flip_f64": (1.162e9, "k_flip.hip", "5713f290969f"),
-    "flip_f32": (5.512e8, "k_flip.hip", "5713f290969f"),
+    "flip_f64": (1.169e9, "k_flip.hip", "f64eca4376ad"),
+    "flip_f32": (5.534e8, "k_flip.hip", "f64eca4376ad"),
     "qr_udv": (2.818e9, "k_qr.hip", "b420df2d0ecd"),
     "qr_solve": (2.952e9, "k_qr.hip", "b420df2d0ecd"),
 }
 # per launch of all 128 chains (the profile pass runs them as one shard)
 TRAFFIC = {
     "dense": dict(_COMMON_TRAFFIC, **{
-        "wrap_f32": (2.047e8, "k_gemm.hip", "acc9d743c719"),
+        "wrap_f32": (1.703e8, "k_gemm.hip", "59e720f1f94b"),
         # mean over every full-size dispatch of the FP64 NN GEMM kernel (wraps,
         # block products and UDV products share it)
-        "wrap_f64": (6.588e8, "k_gemm.hip", "acc9d743c719"),
+        "wrap_f64": (4.528e8, "k_gemm.hip", "59e720f1f94b"),
     }),
     "kronecker": dict(_COMMON_TRAFFIC, **{
         # wraps: one right and one left Kronecker-factor product each (mean of the two)
