@@ -105,6 +105,34 @@ size_t lds_bytes(int N) {
   return d * sizeof(double) + sizeof(int) * (2 * N + 3 * S::NB + 1);
 }
 
+// Cross-lane steps of the panel's reductions by DPP on the vector ALU (a
+// shuffle is a round trip through the LDS crossbar, and the column steps of
+// a panel form one dependent chain).  A butterfly over xor 1, 2, 4 leaves
+// equal values in every quad after its first two steps, so the third step
+// may pair each lane with any lane of the other quad of its 8: the half-row
+// mirror does, and gives the same sums as xor 4.  Likewise the row mirror
+// stands in for xor 8 once each half-row holds one value.
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1, 0, 3, 2]
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane l <-> 7 - l within 8
+constexpr int DPP_MIRROR = 0x140;       // lane l <-> 15 - l within 16
+template <int CTRL> __device__ __forceinline__ int dpp_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ double dpp_dbl(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_int<CTRL>((int)(b & 0xffffffffll)), hi = dpp_int<CTRL>((int)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// sum over each group of 8 lanes, in every lane of the group, with the pairs
+// and the order of a butterfly over xor 1, 2, 4; all 8 lanes must be active
+__device__ __forceinline__ double sum8(double v) {
+  v += dpp_dbl<DPP_XOR1>(v);
+  v += dpp_dbl<DPP_XOR2>(v);
+  v += dpp_dbl<DPP_HALF_MIRROR>(v);
+  return v;
+}
+
 // Unblocked Householder on the LDS panel V[0..m) x [0..w): on return the
 // strict lower part holds v (v_j = 1 implicit), beta[j] = R_jj, tau[j].
 // Eight threads own each column.  With PIVOT the panel's columns are also
@@ -125,27 +153,33 @@ __device__ __forceinline__ void panel_factor(const Lds &s, int m, int w, int *sw
     double a0 = 0.0, a1 = 0.0;
     if (q < w)
       for (int r = sub; r < m; r += 8) { const double x = s.V[r * LDV + q]; a0 += x * x; if (r > 0) a1 += x * x; }
-#pragma unroll
-    for (int o = 1; o < 8; o <<= 1) { a0 += __shfl_xor(a0, o, 64); a1 += __shfl_xor(a1, o, 64); }
+    a0 = sum8(a0);
+    a1 = sum8(a1);
     if (q < w && sub == 0) { s.pn[q] = a0; s.pg[q] = a1; }
     __syncthreads();
   }
   for (int j = 0; j < w; ++j) {
     // pivot: every wavefront finds the first column of largest norm among
-    // j..w-1 (lane q holds column j + q; w <= 64).  The norms of columns
-    // > j are recomputed by their owners below, so pn / pg are not permuted:
-    // the norm of the column moved to j is read at its old position p.
+    // j..w-1 (lane q holds column j + q; w <= 64; a NaN norm ranks last, so
+    // the order is total and the result does not depend on the order of the
+    // reduction).  The norms of columns > j are recomputed by their owners
+    // below, so pn / pg are not permuted: the norm of the column moved to j is
+    // read at its old position p.
     int p = j;
     if (PIVOT) {
       const int lane = t & 63;
       double best = (j + lane < w) ? s.pn[j + lane] : -1.0;
+      if (isnan(best)) best = -1.0;
       p = j + lane;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int op = __shfl_xor(p, o, 64);
+      auto take = [&](double ob, int op) {
         if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
-      }
+      };
+      take(dpp_dbl<DPP_XOR1>(best), dpp_int<DPP_XOR1>(p));
+      take(dpp_dbl<DPP_XOR2>(best), dpp_int<DPP_XOR2>(p));
+      take(dpp_dbl<DPP_HALF_MIRROR>(best), dpp_int<DPP_HALF_MIRROR>(p));
+      take(dpp_dbl<DPP_MIRROR>(best), dpp_int<DPP_MIRROR>(p));
+      take(__shfl_xor(best, 16, 64), __shfl_xor(p, 16, 64));
+      take(__shfl_xor(best, 32, 64), __shfl_xor(p, 32, 64));
       if (p != j) {
         for (int r = t; r < m; r += QT) {
           const double a = s.V[r * LDV + j];
@@ -180,9 +214,7 @@ __device__ __forceinline__ void panel_factor(const Lds &s, int m, int w, int *sw
         for (int u = 0; u < 4; ++u) acc += x[u] * c[u];
       }
       for (; r < m; r += 8) acc += (s.V[r * LDV + j] * scale) * s.V[r * LDV + q];
-      acc += __shfl_xor(acc, 1, 64);
-      acc += __shfl_xor(acc, 2, 64);
-      acc += __shfl_xor(acc, 4, 64);
+      acc = sum8(acc);
       const double f = tj * acc;
       if (sub == 0) s.V[j * LDV + q] -= f;
       r = j + 1 + sub;
@@ -203,8 +235,8 @@ __device__ __forceinline__ void panel_factor(const Lds &s, int m, int w, int *sw
         if (r > j + 1) a1 += v * v; else head = v;
       }
     }
-#pragma unroll
-    for (int o = 1; o < 8; o <<= 1) { a1 += __shfl_xor(a1, o, 64); head += __shfl_xor(head, o, 64); }
+    a1 = sum8(a1);
+    head = sum8(head);
     if (q < w && sub == 0) { s.pg[q] = a1; s.pn[q] = a1 + head * head; }
     __syncthreads();
   }
