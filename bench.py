@@ -44,8 +44,8 @@ HBM_PEAK = 8.0e12
 _COMMON_TRAFFIC = {
     "flip_f64": (1.169e9, "k_flip.hip", "f64eca4376ad"),
     "flip_f32": (5.534e8, "k_flip.hip", "f64eca4376ad"),
-    "qr_udv": (2.818e9, "k_qr.hip", "b420df2d0ecd"),
-    "qr_solve": (2.952e9, "k_qr.hip", "b420df2d0ecd"),
+    "qr_udv": (2.821e9, "k_qr.hip", "65705657108c"),
+    "qr_solve": (2.953e9, "k_qr.hip", "65705657108c"),
 }
 # per launch of all 128 chains (the profile pass runs them as one shard)
 TRAFFIC = {
