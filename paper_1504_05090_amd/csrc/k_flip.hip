@@ -431,7 +431,6 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
   __shared__ double bF[2][2];
   __shared__ double s_R[256];
   __shared__ double red[16];
-  __shared__ int s_acc;
 
   const int N = a.N, t = threadIdx.x, lane = t & 63, w = t >> 6, nw = blockDim.x >> 6;
   typedef PairLanes PL;
@@ -468,10 +467,9 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
   d[0] = own ? (double)G[0][(long)j * N + j] : 0.0;
   d[1] = own ? (double)G[1][(long)j * N + j] : 0.0;
   bool mine = false;
-  if (t == 0) s_acc = 0;
   __syncthreads();
 
-  int m = 0, pos = 0, par = 0;
+  int m = 0, pos = 0, par = 0, nacc = 0;   // nacc: acceptances so far, the same in every lane
   for (;;) {
     bool acc = false;
     if (own && j >= pos) {
@@ -507,8 +505,7 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
       if (hf == 0) {
         bF[par][0] = du / Ru;
         bF[par][1] = dd / Rd;
-        s_R[s_acc] = Ru * Rd;
-        s_acc += 1;
+        s_R[nacc] = Ru * Rd;
         hl[j] = (int8_t)(-hj);
       }
       hj = -hj;
@@ -549,6 +546,7 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
       }
     }
     ++m;
+    ++nacc;
     pos = ist + 1;
     par ^= 1;
     // no barrier: the next acceptance uses the other parity's buffers (see k_flip)
@@ -576,7 +574,6 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
     if (a.trace_mode == 1 && trace_idx >= 0) a.trace[trace_idx] = mine ? 1 : 0;
   }
   __syncthreads();
-  const int nacc = s_acc;
   double lg = 0.0, bad = 0.0;
   for (int q = t; q < nacc; q += blockDim.x) {
     const double R = s_R[q];
