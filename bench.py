@@ -42,8 +42,8 @@ HBM_PEAK = 8.0e12
 # counters were taken on (sha1 prefix); otherwise the traffic is reported as
 # null.
 _COMMON_TRAFFIC = {
-    "flip_f64": (1.169e9, "k_flip.hip", "b23bca4937f7"),
-    "flip_f32": (5.534e8, "k_flip.hip", "b23bca4937f7"),
+    "flip_f64": (1.169e9, "k_flip.hip", "217c6bae88cd"),
+    "flip_f32": (5.534e8, "k_flip.hip", "217c6bae88cd"),
     "qr_udv": (2.821e9, "k_qr.hip", "65705657108c"),
     "qr_solve": (2.953e9, "k_qr.hip", "65705657108c"),
 }

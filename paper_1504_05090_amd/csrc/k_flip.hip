@@ -251,10 +251,10 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
 
 // ---------------------------------------------------------------------------
 // Paired variant for N <= 256: two lanes per site.  Each lane of the pair
-// keeps every other delayed pair (pair m lives in lane m & 1, slot m >> 1),
+// keeps every other delayed pair (pair m lives in half m & 1, slot m >> 1),
 // so the X and Y rows, the dot products of an acceptance and the row that
 // the accepted site publishes are split in half; the halves of a dot product
-// meet through one cross-lane shuffle.  The decision, the diagonal and every
+// meet through one cross-lane swap.  The decision, the diagonal and every
 // value that enters G are the same in both lanes.  Twice the wavefronts also
 // double the loads in flight during a flush.
 
