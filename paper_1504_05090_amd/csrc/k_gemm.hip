@@ -39,6 +39,10 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
   __shared__ T As[2][A_ROWS][A_LD];
   __shared__ T Bs[2][B_ROWS][B_LD];
   __shared__ T Ksh[gemm_ks_max<BM, BN>()];   // A's column scale, staged once
+  // the tile's row and column scales, staged for the big tiles (the small
+  // ones would lose a workgroup per CU to the extra LDS)
+  constexpr bool STAGE = BM >= 128;
+  __shared__ T Rsh[STAGE ? BM : 1], Csh[STAGE ? BN : 1];
 
   const int tilesN = (d.N + BN - 1) / BN;
   const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
@@ -113,6 +117,12 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
 
   const int nk = (d.K + BK - 1) / BK;
   fetch(0);
+  // the epilogue's scales are staged while the first chunk loads, and read
+  // after the main loop's barriers
+  if (STAGE && rs)
+    for (int e = t; e < BM; e += 256) Rsh[e] = i0 + e < d.M ? rs[i0 + e] : (T)0;
+  if (STAGE && cs)
+    for (int e = t; e < BN; e += 256) Csh[e] = j0 + e < d.N ? cs[j0 + e] : (T)0;
   if (ks) {
     for (int e = t; e < d.K; e += 256) Ksh[e] = ks[e];
     __syncthreads();
@@ -149,8 +159,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmDesc d) {
         const int col = j0 + wc * WN + c * 16 + l16;
         if (row < d.M && col < d.N) {
           T v = alpha * acc[a][c][r];
-          if (rs) v *= rs[row];
-          if (cs) v *= cs[col];
+          if (rs) v *= STAGE ? Rsh[row - i0] : rs[row];
+          if (cs) v *= STAGE ? Csh[col - j0] : cs[col];
           T *dst = C + (long)row * d.ldc + col;
           if (beta != (T)0) v += beta * *dst;
           *dst = v;
