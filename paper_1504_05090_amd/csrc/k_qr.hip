@@ -317,15 +317,20 @@ __device__ __forceinline__ void build_T(const Lds &s, int m, int w, int mr) {
     s.T[e] = 0.0;
   }
   __syncthreads();
-  for (int j = 0; j < w; ++j) {
-    double v = 0.0;
-    if (t < j)
-      for (int q = t; q < j; ++q) v += s.T[t * NB + q] * gram[q * NB + j];
-    __syncthreads();
-    if (t < j) s.T[t * NB + j] = -s.tau[j] * v;
-    if (t == 0) s.T[j * NB + j] = s.tau[j];
-    __syncthreads();
+  // the recurrence runs in wavefront 0 (lane t owns row t, w <= 32): its
+  // steps are ordered by wavefront-scope fences instead of block barriers
+  if (wv == 0) {
+    for (int j = 0; j < w; ++j) {
+      double v = 0.0;
+      if (t < j)
+        for (int q = t; q < j; ++q) v += s.T[t * NB + q] * gram[q * NB + j];
+      if (t < j) s.T[t * NB + j] = -s.tau[j] * v;
+      if (t == 0) s.T[j * NB + j] = s.tau[j];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
   }
+  __syncthreads();
   (void)m;
 }
 
