@@ -44,16 +44,16 @@ HBM_PEAK = 8.0e12
 _COMMON_TRAFFIC = {
     "flip_f64": (1.169e9, "k_flip.hip", "217c6bae88cd"),
     "flip_f32": (5.534e8, "k_flip.hip", "217c6bae88cd"),
-    "qr_udv": (2.821e9, "k_qr.hip", "65705657108c"),
-    "qr_solve": (2.953e9, "k_qr.hip", "65705657108c"),
+    "qr_udv": (2.819e9, "k_qr.hip", "59e06fc57d41"),
+    "qr_solve": (2.954e9, "k_qr.hip", "59e06fc57d41"),
 }
 # per launch of all 128 chains (the profile pass runs them as one shard)
 TRAFFIC = {
     "dense": dict(_COMMON_TRAFFIC, **{
-        "wrap_f32": (1.703e8, "k_gemm.hip", "59e720f1f94b"),
+        "wrap_f32": (1.703e8, "k_gemm.hip", "57c2c9444073"),
         # mean over every full-size dispatch of the FP64 NN GEMM kernel (wraps,
         # block products and UDV products share it)
-        "wrap_f64": (4.528e8, "k_gemm.hip", "59e720f1f94b"),
+        "wrap_f64": (4.527e8, "k_gemm.hip", "57c2c9444073"),
     }),
     "kronecker": dict(_COMMON_TRAFFIC, **{
         # wraps: one right and one left Kronecker-factor product each (mean of the two)
