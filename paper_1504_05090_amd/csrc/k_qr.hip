@@ -317,17 +317,27 @@ __device__ __forceinline__ void build_T(const Lds &s, int m, int w, int mr) {
     s.T[e] = 0.0;
   }
   __syncthreads();
-  // the recurrence runs in wavefront 0 (lane t owns row t, w <= 32): its
-  // steps are ordered by wavefront-scope fences instead of block barriers
+  // the recurrence runs in wavefront 0, lane t holding row t of T in
+  // registers (w <= NB <= 32).  Row t is zero left of the diagonal, so
+  // summing from q = 0 adds exact zeros before the terms q >= t: the sums
+  // are those of the recurrence taken from q = t.
   if (wv == 0) {
-    for (int j = 0; j < w; ++j) {
-      double v = 0.0;
-      if (t < j)
-        for (int q = t; q < j; ++q) v += s.T[t * NB + q] * gram[q * NB + j];
-      if (t < j) s.T[t * NB + j] = -s.tau[j] * v;
-      if (t == 0) s.T[j * NB + j] = s.tau[j];
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+    double tr[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) tr[q] = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j < w) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < j; ++q) v += tr[q] * gram[q * NB + j];
+        const double tj = s.tau[j];
+        tr[j] = t < j ? -tj * v : (t == j ? tj : 0.0);
+      }
+    }
+    if (t < NB) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) s.T[t * NB + q] = tr[q];
     }
   }
   __syncthreads();
