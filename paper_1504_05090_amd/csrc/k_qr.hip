@@ -573,10 +573,13 @@ __device__ __forceinline__ void apply(const Lds &s, double *X, long ldx, int r0,
 // index first) into positions [c0, c0 + w), in order of decreasing norm; the
 // columns they displace take the vacated positions (k-th displaced column,
 // by position, to the k-th vacated position).  Whole columns move, so the R
-// rows above the panel stay consistent; the chosen columns are staged in the
-// (still free) panel area of LDS.
+// rows above the panel stay consistent.  The chosen columns are staged in
+// LDS: rows >= c0 straight into the panel layout (V[r - c0], zero-padded to
+// mr x NB), which is what the factorisation loads, and rows < c0 below them
+// (V[m + r]) until they are written back to A.  The panel rows of A itself
+// are written when the factored panel is stored.
 template <class S>
-__device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int c0, int w) {
+__device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int c0, int w, int m, int mr) {
   constexpr int LDV = S::LDV;
   const int t = threadIdx.x;
   int *rank = s.sel;          // [N]
@@ -618,9 +621,10 @@ __device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int
   __syncthreads();
   const int nd = min(*nmv, w);
   // stage chosen columns (all rows), move the displaced ones, write back
+  // the rows above the panel
   for (int e = t; e < N * w; e += QT) {
     const int r = e / w, i = e % w;
-    s.V[r * LDV + i] = A[(long)r * N + src[i]];
+    s.V[(r >= c0 ? r - c0 : m + r) * LDV + i] = A[(long)r * N + src[i]];
   }
   int o_i = 0, o_d = 0;
   double n_i = 0.0, n_d = 0.0;
@@ -633,11 +637,18 @@ __device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int
   }
   if (t < nd) { s.orig[mv_to[t]] = o_d; s.norms[mv_to[t]] = n_d; }
   __syncthreads();
-  for (int e = t; e < N * w; e += QT) {
+  for (int e = t; e < c0 * w; e += QT) {
     const int r = e / w, i = e % w;
-    A[(long)r * N + c0 + i] = s.V[r * LDV + i];
+    A[(long)r * N + c0 + i] = s.V[(m + r) * LDV + i];
   }
   if (t < w) { s.orig[c0 + t] = o_i; s.norms[c0 + t] = n_i; }
+  __syncthreads();
+  // zero padding of the panel: rows [m, mr) (which held the rows above the
+  // panel) and columns [w, NB)
+  for (int e = t; e < mr * S::NB; e += QT) {
+    const int r = e / S::NB, q = e % S::NB;
+    if (r >= m || q >= w) s.V[r * LDV + q] = 0.0;
+  }
   __syncthreads();
 }
 
@@ -650,13 +661,16 @@ __device__ __forceinline__ void factor(const Lds &s, double *A, double *Tsave, d
   QR_TICK_INIT;
   for (int c0 = 0; c0 < N; c0 += NB) {
     const int w = min(NB, N - c0), m = N - c0, mr = round16(m);
-    if (PIVOT) select_panel<S>(s, A, N, c0, w);
-    QR_TICK(0);
-    for (int e = threadIdx.x; e < mr * NB; e += QT) {
-      const int r = e / NB, q = e % NB;
-      s.V[r * LDV + q] = (r < m && q < w) ? A[(long)(c0 + r) * N + c0 + q] : 0.0;
+    if (PIVOT) {
+      select_panel<S>(s, A, N, c0, w, m, mr);   // leaves the panel in V
+    } else {
+      for (int e = threadIdx.x; e < mr * NB; e += QT) {
+        const int r = e / NB, q = e % NB;
+        s.V[r * LDV + q] = (r < m && q < w) ? A[(long)(c0 + r) * N + c0 + q] : 0.0;
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    QR_TICK(0);
     QR_TICK(1);
     panel_factor<S, PIVOT>(s, m, w, s.sel);
     if (PIVOT) {
