@@ -724,8 +724,17 @@ __global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long 
   {
     QR_TICK_INIT;
     for (int q = t; q < N; q += QT) {
+      // sixteen rows' loads in flight per step; the sum keeps the row order
       double acc = 0.0;
-      for (int r = 0; r < N; ++r) { const double x = X[(long)r * N + q]; acc += x * x; }
+      int r = 0;
+      for (; r + 16 <= N; r += 16) {
+        double x[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) x[u] = X[(long)(r + u) * N + q];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += x[u] * x[u];
+      }
+      for (; r < N; ++r) { const double x = X[(long)r * N + q]; acc += x * x; }
       s.norms[q] = acc;
       s.orig[q] = q;
     }
