@@ -744,10 +744,28 @@ __global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long 
   factor<S, true>(s, X, Ts, scr, N, nullptr, 0);
   // D = diag R,  RP[i][orig[q]] = R[i][q] / R[i][i]
   for (int i = t; i < N; i += QT) D[i] = X[(long)i * N + i];
-  for (long e = t; e < NN; e += QT) {
-    const int i = (int)(e / N), q = (int)(e % N);
-    const double v = q < i ? 0.0 : (q == i ? 1.0 : X[e] / X[(long)i * N + i]);
-    RP[(long)i * N + s.orig[q]] = v;
+  // eight elements' loads in flight per step
+  for (long e0 = t; e0 < NN; e0 += 8L * QT) {
+    double xv[8], dv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const long e = e0 + (long)k * QT;
+      xv[k] = dv[k] = 1.0;
+      if (e < NN) {
+        const int i = (int)(e / N);
+        xv[k] = X[e];
+        dv[k] = X[(long)i * N + i];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const long e = e0 + (long)k * QT;
+      if (e < NN) {
+        const int i = (int)(e / N), q = (int)(e % N);
+        const double v = q < i ? 0.0 : (q == i ? 1.0 : xv[k] / dv[k]);
+        RP[(long)i * N + s.orig[q]] = v;
+      }
+    }
   }
   // Q = Q_0 Q_1 ... applied in reverse order to the identity
   for (long e = t; e < NN; e += QT) U[e] = ((e / N) == (e % N)) ? 1.0 : 0.0;
