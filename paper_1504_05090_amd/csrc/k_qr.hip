@@ -270,9 +270,12 @@ __device__ __forceinline__ void panel_store_clean(const Lds &s, double *A, int N
 template <class S>
 __device__ __forceinline__ void panel_load_clean(const Lds &s, const double *A, int N, int c0, int m, int w, int mr) {
   constexpr int LDV = S::LDV;
+  // unconditional loads from clamped addresses, eight in flight per thread
+#pragma unroll 8
   for (int e = threadIdx.x; e < mr * S::NB; e += QT) {
     const int r = e / S::NB, q = e % S::NB;
-    const double v = (q >= w || r >= m || r < q) ? 0.0 : (r == q ? 1.0 : A[(long)(c0 + r) * N + c0 + q]);
+    const double a = A[(long)(c0 + min(r, m - 1)) * N + c0 + min(q, w - 1)];
+    const double v = (q >= w || r >= m || r < q) ? 0.0 : (r == q ? 1.0 : a);
     s.V[r * LDV + q] = v;
   }
   __syncthreads();
@@ -622,6 +625,7 @@ __device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int
   const int nd = min(*nmv, w);
   // stage chosen columns (all rows), move the displaced ones, write back
   // the rows above the panel
+#pragma unroll 8
   for (int e = t; e < N * w; e += QT) {
     const int r = e / w, i = e % w;
     s.V[(r >= c0 ? r - c0 : m + r) * LDV + i] = A[(long)r * N + src[i]];
@@ -631,6 +635,7 @@ __device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int
   if (t < w) { o_i = s.orig[src[t]]; n_i = s.norms[src[t]]; }
   if (t < nd) { o_d = s.orig[mv_from[t]]; n_d = s.norms[mv_from[t]]; }
   __syncthreads();
+#pragma unroll 8
   for (int e = t; e < N * nd; e += QT) {
     const int r = e / nd, i = e % nd;
     A[(long)r * N + mv_to[i]] = A[(long)r * N + mv_from[i]];
@@ -664,9 +669,11 @@ __device__ __forceinline__ void factor(const Lds &s, double *A, double *Tsave, d
     if (PIVOT) {
       select_panel<S>(s, A, N, c0, w, m, mr);   // leaves the panel in V
     } else {
+#pragma unroll 8
       for (int e = threadIdx.x; e < mr * NB; e += QT) {
         const int r = e / NB, q = e % NB;
-        s.V[r * LDV + q] = (r < m && q < w) ? A[(long)(c0 + r) * N + c0 + q] : 0.0;
+        const double a = A[(long)(c0 + min(r, m - 1)) * N + c0 + min(q, w - 1)];
+        s.V[r * LDV + q] = (r < m && q < w) ? a : 0.0;
       }
       __syncthreads();
     }
@@ -805,9 +812,11 @@ __global__ __launch_bounds__(QT) void k_qr_solve(double *Mall, double *Ball, dou
   for (int p = np - 1; p >= 0; --p) {
     const int r0 = p * NB, w = min(NB, N - r0), k0 = r0 + w, kn = N - k0;
     if (kn > 0) {   // Y_p -= R[r0:r0+w, k0:N] Z[k0:N, :]
+#pragma unroll 8
       for (int e = t; e < NB * kn; e += QT) {
         const int i = e / kn, k = e % kn;
-        Rs[i * RLD + k] = (i < w) ? M[(long)(r0 + i) * N + k0 + k] : 0.0;
+        const double a = M[(long)(r0 + min(i, w - 1)) * N + k0 + k];
+        Rs[i * RLD + k] = (i < w) ? a : 0.0;
       }
       __syncthreads();
       // one 16-column tile per wavefront at a time, for every row tile of the
