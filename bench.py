@@ -44,8 +44,8 @@ HBM_PEAK = 8.0e12
 _COMMON_TRAFFIC = {
     "flip_f64": (1.169e9, "k_flip.hip", "217c6bae88cd"),
     "flip_f32": (5.534e8, "k_flip.hip", "217c6bae88cd"),
-    "qr_udv": (2.819e9, "k_qr.hip", "59e06fc57d41"),
-    "qr_solve": (2.954e9, "k_qr.hip", "59e06fc57d41"),
+    "qr_udv": (2.775e9, "k_qr.hip", "4ca8710ab0ca"),
+    "qr_solve": (2.953e9, "k_qr.hip", "4ca8710ab0ca"),
 }
 # per launch of all 128 chains (the profile pass runs them as one shard)
 TRAFFIC = {
