@@ -591,6 +591,10 @@ int orc_step_slices(orc_chain *c, int n, const uint8_t *forced, uint8_t *trace) 
       double Ru, Rd;
       orc_ratio(c, l, i, &Ru, &Rd);
       double R = Ru * Rd;
+      /* At half filling every weight of eq. (3) is positive, so a ratio that
+       * is not a finite positive number means the Green function is broken:
+       * that is an error whether or not the flip is accepted. */
+      const int bad = !(R > 0) || !isfinite(R);
       int acc;
       if (forced) {
         acc = forced[idx] != 0;
@@ -601,8 +605,11 @@ int orc_step_slices(orc_chain *c, int n, const uint8_t *forced, uint8_t *trace) 
       if (trace) trace[idx] = (uint8_t)acc;
       c->st.proposals++;
       if (acc) {
-        if (!(R > 0) || !isfinite(R)) { c->st.error = 1; rc = -1; break; }
         c->st.accepted++;
+        if (R < 0) c->st.sign = -c->st.sign;   /* sign of the weight, eq. (3) */
+      }
+      if (bad) { c->st.error = 1; rc = -1; break; }
+      if (acc) {
         c->st.logw += log(R);
         orc_accept_update(c, l, i);
       }

@@ -74,7 +74,9 @@ void orc_set_green(orc_chain *c, int spin, const double *in);
 /* Advance n slices.  forced != NULL: accept bits (one byte per proposal, in
  * visiting order) replace the Metropolis test.  trace != NULL: the accept
  * decisions taken are written there (one byte per proposal).
- * Returns 0, or -1 if a non-finite or non-positive ratio was met. */
+ * Returns 0, or -1 if a proposal's ratio R = R_up R_dn was non-finite or
+ * non-positive (accepted or not); the chain then stops at that proposal with
+ * its error flag set. */
 int orc_step_slices(orc_chain *c, int n, const uint8_t *forced, uint8_t *trace);
 
 /* single pieces of the sweep, exposed for the unit tests */
@@ -101,8 +103,10 @@ typedef struct {
   int64_t proposals, accepted;
   double drift_max, drift_sum;
   int64_t drift_count;
-  double logw;          /* running sum of log|R| over accepted flips */
-  int sign;             /* running product of sgn R */
+  double logw;          /* running sum of log R over accepted flips */
+  int sign;             /* running product of sgn R over accepted flips (a
+                           negative ratio is also an error, so it stays +1
+                           on a healthy chain) */
   int error;            /* nonzero after a numerical failure */
 } orc_stats;
 void orc_get_stats(const orc_chain *c, orc_stats *out);

@@ -157,3 +157,89 @@ def test_detailed_balance_chi2(orc):
     pval = chi2.sf(stat, len(fields) - 1)
     assert pval > 1e-3, (stat, pval)
     assert p.max() / p.min() > 2     # the target is far from uniform
+
+
+def _numpy_uniform(key0, key1, s, pos):
+    """u of the Metropolis test from numpy's own Philox4x64-10: word 0 of the
+    block at counter (s, pos, 0, 0) under key (key0, key1), top 53 bits
+    scaled by 2^-53.  numpy bumps the counter before producing a block, so
+    its state starts one below."""
+    words = [s, pos, 0, 0]
+    for k in range(4):            # subtract one from the 256-bit counter
+        if words[k] > 0:
+            words[k] -= 1
+            break
+        words[k] = 2**64 - 1
+    ctr = np.array(words, dtype=np.uint64)
+    bg = np.random.Philox(key=np.array([key0, key1], dtype=np.uint64), counter=ctr)
+    w0 = int(bg.random_raw(1)[0])
+    return (w0 >> 11) * 2.0 ** -53
+
+
+def test_metropolis_draw_against_numpy_philox(orc):
+    """The accept decisions of a free-running chain are those of the
+    Metropolis test u < R with u from numpy's Philox at counter
+    (sweep, (l-1) N + i, 0, 0) and key (seed + chain, instance): the chain is
+    replayed proposal by proposal with the oracle's own ratio, update, wrap
+    and recomputation pieces and numpy's draws, over two sweeps (so the sweep
+    index enters), on a chain whose acceptance is far from 0 and 1."""
+    L, U, beta, dtau, n_stab, seed, inst, chain = 4, 2.0, 1.0, 0.5, 2, 4711, 3, 5
+    a = orc.Chain(L, U, T, beta, dtau, seed, inst, chain, n_stab)
+    want = a.sweep(2, record=True)
+    b = orc.Chain(L, U, T, beta, dtau, seed, inst, chain, n_stab)
+    N, lam = b.N, b.Lam
+    got = []
+    for s in range(2):
+        for l in range(1, lam + 1):
+            for i in range(N):
+                ru, rd = b.ratio(l, i)
+                u = _numpy_uniform(seed + chain, inst, s, (l - 1) * N + i)
+                acc = u < ru * rd
+                got.append(acc)
+                if acc:
+                    b.accept_update(l, i)
+            b.wrap(l)
+            if l % n_stab == 0 or l == lam:
+                nxt = 1 if l == lam else l + 1
+                fresh = [b.fresh_green(nxt, sp) for sp in range(2)]
+                for sp in range(2):
+                    b.set_green(sp, fresh[sp])
+    got = np.array(got, dtype=np.uint8)
+    assert 0.2 < got.mean() < 0.8
+    assert np.array_equal(got, want)
+    assert np.array_equal(a.field(), b.field())
+
+
+def _broken_green_chain(orc, value):
+    c = orc.Chain(4, 2.0, T, 2.0, 0.5, 31, 0, 0, 2)
+    for sp in range(2):
+        c.set_green(sp, np.eye(c.N) * value)
+    return c
+
+
+@pytest.mark.parametrize("value", [float("nan"), 5.0], ids=["nan", "negative_ratio"])
+def test_bad_ratio_is_an_error_even_when_rejected(orc, value):
+    """A Green function whose diagonal is NaN, or so large that R <= 0, is a
+    numerical failure (every weight of eq. (3) is positive at half filling):
+    the free-running chain stops with its error flag set at the first such
+    proposal, although the Metropolis test would simply reject it."""
+    c = _broken_green_chain(orc, value)
+    with pytest.raises(FloatingPointError):
+        c.step_slices(1)
+    st = c.stats()
+    assert st["error"] == 1 and st["proposals"] == 1 and st["accepted"] == 0
+    if value == 5.0:
+        ru, rd = c.ratio(1, 0)
+        assert ru * rd < 0
+
+
+def test_forced_negative_ratio_flips_the_sign_and_stops(orc):
+    """A forced acceptance of a negative ratio multiplies the running sign by
+    -1, and the chain stops there with the error flag set."""
+    c = _broken_green_chain(orc, 5.0)
+    with pytest.raises(FloatingPointError):
+        c.step_slices(1, forced=np.ones(c.N, np.uint8))
+    st = c.stats()
+    assert st["error"] == 1 and st["accepted"] == 1 and st["sign"] == -1
+    h = orc.Chain(4, 2.0, T, 2.0, 0.5, 31, 0, 0, 2)
+    assert np.array_equal(c.field(), h.field())   # the bad flip was not applied
