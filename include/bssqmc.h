@@ -39,11 +39,13 @@
  *
  * Errors
  *   Every call returns a bss_status; nothing throws or aborts across the ABI.
- *   A numerical failure (non-finite or non-positive accepted ratio, or a wrap
- *   drift above bss_options.drift_abort) poisons the context: the call that
- *   detects it returns BSS_E_NUMERICAL and later calls return BSS_E_STATE.
- *   Since sweeps are asynchronous, a failure inside a sweep is reported by
- *   the next synchronising call.
+ *   A numerical failure poisons the context: the call that detects it
+ *   returns BSS_E_NUMERICAL and later calls return BSS_E_STATE.  Failures are
+ *   a proposal whose ratio R is not a finite positive number (accepted or
+ *   not: every weight of eq. (3) is positive at half filling), a non-finite
+ *   wrapped or recomputed Green function, and a relative wrap drift above
+ *   bss_options.drift_abort.  Since sweeps are asynchronous, a failure inside
+ *   a sweep is reported by the next synchronising call.
  */
 #ifndef BSSQMC_H
 #define BSSQMC_H
@@ -104,15 +106,28 @@ typedef struct {
   void *workspace;       /* optional device memory for all state (caller-owned)    */
   size_t workspace_bytes;
   uint32_t flags;        /* BSS_FLAG_*                                             */
-  double drift_abort;    /* poison the context if the wrap drift exceeds this;
-                            0 = never                                              */
+  double drift_abort;    /* poison the context if a relative wrap drift
+                            max_ij |G_wrapped - G_fresh| / max(1, max_ij |G_fresh|)
+                            exceeds this; 0 = never.  Default 0.1: far above the
+                            drift of either precision, far below a chain whose
+                            ratios no longer mean anything                        */
   int32_t trace_sweeps;  /* capacity of the record buffer, in sweeps               */
   int32_t fp32_slices;   /* BSS_PREC_MIXED: FP32 slices at the end of each block
-                            (values >= n_stab: every slice); 0 = automatic, the
-                            largest count s whose estimated mean FP32 drift
-                            2^-24 e^{2 lambda s} stays below 1e-5 (may be 0,
-                            i.e. all FP64, at strong coupling).  Ignored in
+                            (values >= n_stab: every slice).  0 = automatic: a
+                            drift controller.  Sweeps start with no FP32 slice;
+                            after every sweep the library reads the largest
+                            relative wrap drift d of each instance's chains in
+                            that sweep and moves the next sweep's count by one:
+                            down if d > fp32_drift_target / 2, up if
+                            d e^{2 lambda} < fp32_drift_target / 2 (one more
+                            FP32 slice multiplies the FP32 part of the drift by
+                            about e^{2 lambda}), never above the largest s with
+                            2^-24 e^{2 lambda s} <= 1e-5 (may be 0 at strong
+                            coupling).  bss_sweep then waits for each sweep's
+                            recomputations before issuing the next.  Ignored in
                             FP64 mode.                                             */
+  double fp32_drift_target; /* the controller's bound on the relative drift;
+                            0 = 1e-3                                              */
 } bss_options;
 
 /* One (L, U, t, beta, dtau) instance with its chains. */
@@ -130,15 +145,19 @@ typedef struct {
   double drift_max;      /* max_ij |G_wrapped - G_fresh| over recomputations       */
   double drift_mean;
   double logw;           /* sum over chains of sum log R over accepted flips       */
-  int32_t sign;          /* product of sgn R over accepted flips (always +1 here)  */
+  int32_t sign;          /* product of sgn R over accepted flips (a negative ratio
+                            is also a numerical failure, so +1 on a healthy run) */
   int32_t n_chains;
   int32_t N, Lambda, delay_k, n_stab;  /* resolved parameters                      */
-  int32_t fp32_slices;   /* resolved FP32 slices per block (0 in FP64 mode)        */
+  int32_t fp32_slices;   /* FP32 slices per block of the next sweep (0 in FP64
+                            mode; the controller's current count when automatic) */
   double drift_rel_max;  /* drift over max(1, max_ij |G_fresh|), per recomputation */
   double drift_rel_mean;
   int32_t sweep_graph;   /* 1 once bss_sweep replays a captured hipGraph          */
   int32_t shards;        /* chain groups the instance is split into, each on its
                             own streams (every kernel launch covers one group)  */
+  double fp32_fraction;  /* fraction of the slices swept since creation or the
+                            last bss_reset_stats that ran in FP32               */
 } bss_stats;
 
 /* Per-kernel launch timing collected under BSS_FLAG_PROFILE. */
@@ -274,6 +293,15 @@ typedef struct {
  * trial_sweeps < 1, or an invalid instance or options. */
 bss_status bss_autotune(const bss_instance *inst, const bss_options *base, double drift_bound,
                         int32_t warmup_sweeps, int32_t trial_sweeps, bss_tune_result *out);
+
+/* Overwrite element (i, j) of the current Green function of one chain and
+ * spin (in the precision the current slice holds it) with `value`, e.g. a NaN
+ * or a value outside [0, 1] on the diagonal.  For tests of the failure
+ * handling above: the next sweep meets the broken G as a numerical failure
+ * would arise, and every kernel still runs to its end.  Synchronises.
+ * INVALID_ARG: bad instance, chain, spin or indices. */
+bss_status bss_debug_set_green(bss_ctx *c, int32_t inst, int32_t chain, int32_t spin, int32_t i, int32_t j,
+                               double value);
 
 /* Release the context (NULL is allowed). */
 void bss_destroy(bss_ctx *c);

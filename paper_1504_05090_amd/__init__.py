@@ -26,7 +26,7 @@ EXPORTS = [
     "bss_step_slices", "bss_measure_gtau_k", "bss_measure_double_occ", "bss_reset_measurements", "bss_reset_stats", "bss_synchronize",
     "bss_get_green", "bss_get_field", "bss_set_field", "bss_set_trace", "bss_get_trace",
     "bss_get_stats", "bss_save", "bss_load", "bss_destroy", "bss_status_string", "bss_last_error",
-    "bss_get_profile", "bss_reset_profile", "bss_autotune",
+    "bss_get_profile", "bss_reset_profile", "bss_autotune", "bss_debug_set_green",
 ]
 
 
@@ -34,7 +34,8 @@ class Options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("delay_k", ctypes.c_int32),
                 ("n_stab", ctypes.c_int32), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("flags", ctypes.c_uint32), ("drift_abort", ctypes.c_double),
-                ("trace_sweeps", ctypes.c_int32), ("fp32_slices", ctypes.c_int32)]
+                ("trace_sweeps", ctypes.c_int32), ("fp32_slices", ctypes.c_int32),
+                ("fp32_drift_target", ctypes.c_double)]
 
 
 class Instance(ctypes.Structure):
@@ -48,7 +49,8 @@ class Stats(ctypes.Structure):
                 ("sign", ctypes.c_int32), ("n_chains", ctypes.c_int32), ("N", ctypes.c_int32),
                 ("Lambda", ctypes.c_int32), ("delay_k", ctypes.c_int32), ("n_stab", ctypes.c_int32),
                 ("fp32_slices", ctypes.c_int32), ("drift_rel_max", ctypes.c_double),
-                ("drift_rel_mean", ctypes.c_double), ("sweep_graph", ctypes.c_int32), ("shards", ctypes.c_int32)]
+                ("drift_rel_mean", ctypes.c_double), ("sweep_graph", ctypes.c_int32), ("shards", ctypes.c_int32),
+                ("fp32_fraction", ctypes.c_double)]
 
 
 class TuneResult(ctypes.Structure):
@@ -103,6 +105,7 @@ def lib():
         L.bss_get_profile.argtypes = [vp, P(KernelTime), i32, P(i32)]
         L.bss_reset_profile.argtypes = [vp]
         L.bss_autotune.argtypes = [P(Instance), P(Options), dbl, i32, i32, P(TuneResult)]
+        L.bss_debug_set_green.argtypes = [vp, i32, i32, i32, i32, i32, dbl]
         L.bss_destroy.argtypes = [vp]
         L.bss_destroy.restype = None
         L.bss_status_string.argtypes = [i32]
@@ -121,14 +124,19 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def make_options(precision="fp64", delay_k=0, n_stab=0, flags=0, trace_sweeps=0, drift_abort=0.0,
-                 stream=None, workspace=None, workspace_bytes=0, fp32_slices=0) -> Options:
+def make_options(precision="fp64", delay_k=0, n_stab=0, flags=0, trace_sweeps=0, drift_abort=None,
+                 stream=None, workspace=None, workspace_bytes=0, fp32_slices=0, fp32_drift_target=0.0) -> Options:
+    """bss_options from the library's defaults; drift_abort=None keeps the
+    library's default."""
     o = Options()
     lib().bss_options_default(ctypes.byref(o))
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     o.delay_k, o.n_stab, o.flags = delay_k, n_stab, flags
-    o.trace_sweeps, o.drift_abort = trace_sweeps, drift_abort
+    o.trace_sweeps = trace_sweeps
+    if drift_abort is not None:
+        o.drift_abort = drift_abort
     o.fp32_slices = fp32_slices
+    o.fp32_drift_target = fp32_drift_target
     o.stream = stream
     o.workspace = workspace
     o.workspace_bytes = workspace_bytes
@@ -144,7 +152,7 @@ class Context:
     """
 
     def __init__(self, instances, precision="fp64", delay_k=0, n_stab=0, flags=0, trace_sweeps=0,
-                 drift_abort=0.0, stream=None, fp32_slices=0):
+                 drift_abort=None, stream=None, fp32_slices=0, fp32_drift_target=0.0):
         import torch  # device memory and streams only
 
         if not torch.cuda.is_available():
@@ -159,7 +167,8 @@ class Context:
         self.n_inst = len(instances)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         opt = make_options(precision, delay_k, n_stab, flags, trace_sweeps, drift_abort,
-                           stream=self._stream.cuda_stream, fp32_slices=fp32_slices)
+                           stream=self._stream.cuda_stream, fp32_slices=fp32_slices,
+                           fp32_drift_target=fp32_drift_target)
         nbytes = ctypes.c_size_t()
         self._check(L.bss_workspace_size(arr, len(instances), ctypes.byref(opt), ctypes.byref(nbytes)),
                     "bss_workspace_size")
@@ -239,6 +248,11 @@ class Context:
         a = np.zeros(n_sweeps * p["n_chains"] * p["Lambda"] * p["N"], dtype=np.uint8)
         self._check(lib().bss_get_trace(self._h, inst, _ptr(a), n_sweeps), "bss_get_trace")
         return a.reshape(n_sweeps, p["n_chains"], p["Lambda"], p["N"])
+
+    def debug_set_green(self, value, inst=0, chain=0, spin=0, i=0, j=0):
+        """Overwrite one element of a chain's current G (failure-handling tests)."""
+        self._check(lib().bss_debug_set_green(self._h, inst, chain, spin, i, j, float(value)),
+                    "bss_debug_set_green")
 
     def stats(self, inst=0) -> dict:
         s = Stats()

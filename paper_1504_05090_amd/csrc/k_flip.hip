@@ -140,6 +140,7 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
   __syncthreads();
 
   int m = 0, pos = 0, par = 0;
+  bool badj = false;
   for (;;) {
     bool acc = false;
     if (own && j >= pos) {
@@ -147,6 +148,10 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
       const double dd = hj > 0 ? a.dlt_dn_p : a.dlt_dn_m;
       const double R = (1.0 + (1.0 - d[0]) * du) * (1.0 + (1.0 - d[1]) * dd);
       acc = (a.trace_mode == 2) ? forced : (uj < R);
+      // the last evaluation is the site's proposal: every weight of eq. (3)
+      // is positive at half filling, so a ratio that is not a finite positive
+      // number is an error whether or not it is accepted
+      badj = !(R > 0.0) || !isfinite(R);
     }
     const unsigned long long bal = __ballot(acc);
     if (lane == 0) first[par][w] = bal ? (w * 64 + __ffsll((long long)bal) - 1) : 0x7fffffff;
@@ -230,21 +235,24 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
   }
   __syncthreads();
   // log-weight of the slice's accepted ratios (FP64), and the check that
-  // every accepted ratio was positive and finite
+  // every proposed ratio was positive and finite
   const int nacc = s_acc;
-  double lg = 0.0, bad = 0.0;
+  double lg = 0.0, bad = badj ? 1.0 : 0.0, neg = 0.0;
   for (int q = j; q < nacc; q += blockDim.x) {
     const double R = s_R[q];
     if (!(R > 0.0) || !isfinite(R)) bad = 1.0;
-    lg += log(R);
+    if (R < 0.0) neg += 1.0;
+    lg += log(fabs(R));
   }
   lg = block_sum(lg, red);
   bad = block_max(bad, red);
+  neg = block_sum(neg, red);
   if (j == 0) {
     ChainStats *st = a.stats + c;
     st->proposals += N;
     st->accepted += nacc;
     st->logw += lg;
+    st->negs += (int)neg;
     if (bad > 0.0) atomicOr(a.err, 1);
   }
 }
@@ -470,6 +478,7 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
   __syncthreads();
 
   int m = 0, pos = 0, par = 0, nacc = 0;   // nacc: acceptances so far, the same in every lane
+  bool badj = false;
   for (;;) {
     bool acc = false;
     if (own && j >= pos) {
@@ -477,6 +486,10 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
       const double dd = hj > 0 ? a.dlt_dn_p : a.dlt_dn_m;
       const double R = (1.0 + (1.0 - d[0]) * du) * (1.0 + (1.0 - d[1]) * dd);
       acc = (a.trace_mode == 2) ? forced : (uj < R);
+      // the last evaluation is the site's proposal: every weight of eq. (3)
+      // is positive at half filling, so a ratio that is not a finite positive
+      // number is an error whether or not it is accepted
+      badj = !(R > 0.0) || !isfinite(R);
     }
     // both lanes of a site decide alike: look at the lanes of half 0
     const unsigned long long bal = __ballot(acc) & PL::half0;
@@ -574,19 +587,22 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
     if (a.trace_mode == 1 && trace_idx >= 0) a.trace[trace_idx] = mine ? 1 : 0;
   }
   __syncthreads();
-  double lg = 0.0, bad = 0.0;
+  double lg = 0.0, bad = badj ? 1.0 : 0.0, neg = 0.0;
   for (int q = t; q < nacc; q += blockDim.x) {
     const double R = s_R[q];
     if (!(R > 0.0) || !isfinite(R)) bad = 1.0;
-    lg += log(R);
+    if (R < 0.0) neg += 1.0;
+    lg += log(fabs(R));
   }
   lg = block_sum(lg, red);
   bad = block_max(bad, red);
+  neg = block_sum(neg, red);
   if (t == 0) {
     ChainStats *st = a.stats + c;
     st->proposals += N;
     st->accepted += nacc;
     st->logw += lg;
+    st->negs += (int)neg;
     if (bad > 0.0) atomicOr(a.err, 1);
   }
 }

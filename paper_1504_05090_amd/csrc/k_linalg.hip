@@ -200,9 +200,11 @@ __global__ __launch_bounds__(256) void k_drift_part(const Tc *Gc, To *Go, const 
   double dmax = 0.0, gmax = 0.0;
   bool bad = false;
   for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-    const double f = gf[e];
-    if (!isfinite(f)) bad = true;
-    dmax = fmax(dmax, fabs((double)gc[e] - f));
+    const double f = gf[e], g = (double)gc[e];
+    // a non-finite fresh or wrapped G is a numerical failure (fmax would
+    // drop a NaN difference)
+    if (!isfinite(f) || !isfinite(g)) bad = true;
+    dmax = fmax(dmax, fabs(g - f));
     gmax = fmax(gmax, fabs(f));
     go[e] = (To)f;
   }
@@ -232,8 +234,9 @@ __global__ __launch_bounds__(64) void k_drift_final(const double *part, ChainSta
       st->drift_sum += dm;
       st->rdrift_max = fmax(st->rdrift_max, rel);
       st->rdrift_sum += rel;
+      st->rdrift_sweep = count == 2 ? rel : fmax(st->rdrift_sweep, rel);
       st->drift_count += 1;
-      if (drift_abort > 0.0 && dm > drift_abort) atomicOr(err, 2);
+      if (drift_abort > 0.0 && rel > drift_abort) atomicOr(err, 2);
     }
     if (anybad > 0.0) atomicOr(err, 4);
   }
@@ -275,10 +278,10 @@ hipError_t time_rhs(const double *DR, const double *VR, double *RHS, int mats, i
 }
 
 hipError_t drift_replace(const void *Gc, bool cmp64, void *Go, bool out64, const double *Gf, int chains, int N,
-                         double *part, ChainStats *stats, int *err, double drift_abort, bool count, hipStream_t s) {
+                         double *part, ChainStats *stats, int *err, double drift_abort, int count, hipStream_t s) {
   if (chains <= 0) return hipSuccess;
-  if (chains > 65535 || !part) return hipErrorInvalidValue;
-  const int cnt = count ? 1 : 0;
+  if (chains > 65535 || !part || count < 0 || count > 2) return hipErrorInvalidValue;
+  const int cnt = count;
   const dim3 g(DRIFT_PARTS, chains), b(256);
   if (cmp64 && out64)
     hipLaunchKernelGGL((k_drift_part<double, double>), g, b, 0, s, (const double *)Gc, (double *)Go, Gf, N, part);

@@ -8,11 +8,17 @@
 //   W = V^T C,   C <- C - V (T^T W),
 // the chunk C staying in registers in the MFMA accumulator layout.
 //
-// Pivoting for the UDV factorisation: before each panel the remaining columns
-// are ranked by their current norms (accumulated while the previous panel's
-// update streams through them) and the NB largest are swapped into the panel.
-// For the graded products X = P U D this orders the scales as Businger-Golub
-// column pivoting does, at the cost of one norm per column per panel.
+// Pivoting for the UDV factorisation follows Businger-Golub: every pivot is
+// the remaining column of largest norm.  Before each panel the remaining
+// columns are ranked by their current norms (accumulated while the previous
+// panel's update streams through them) and the NB largest are swapped into
+// the panel, where the pivots are searched column by column.  A column's norm
+// over the remaining rows never grows under the panel's reflections, so while
+// the best in-panel norm is at least the largest norm left outside the panel
+// (taken at the panel's start), the in-panel pivot is the global one.  When
+// it falls below, the panel ends there and its unfactored columns go back to
+// the trailing matrix: panels have variable width, and |R_ij| <= |R_ii| holds
+// as it does for unblocked Businger-Golub pivoting.
 //
 //   qr_udv:   X Pi = Q R  ->  U = Q, D = diag R, RP = D^{-1} R Pi^T
 //   qr_solve: M Z = B by M = Q R (no pivoting), Z = R^{-1} Q^T B
@@ -26,23 +32,6 @@ namespace {
 constexpr int QT = 256;   // 4 wavefronts
 typedef Mfma<double> M64;
 
-#ifdef BSS_QR_TIMING
-// phase timers of workgroup 0 (diagnostic builds only)
-__device__ unsigned long long qr_phase_ticks[16];
-#define QR_TICK(id)                                                          \
-  do {                                                                       \
-    __syncthreads();                                                         \
-    if (blockIdx.x == 0 && threadIdx.x == 0) {                               \
-      const unsigned long long now_ = clock64();                             \
-      qr_phase_ticks[id] += now_ - qr_tick_last;                             \
-      qr_tick_last = now_;                                                   \
-    }                                                                        \
-  } while (0)
-#define QR_TICK_INIT unsigned long long qr_tick_last = clock64()
-#else
-#define QR_TICK(id) do {} while (0)
-#define QR_TICK_INIT do {} while (0)
-#endif
 
 // per-shape constants: panel width NB, chunk width CW, max row tiles per wave;
 // COLS: block reflectors applied by whole-column tiles per wavefront
@@ -70,6 +59,7 @@ struct Lds {
   double *pn;     // [NB] in-panel pivot norms (rows >= j)
   double *pg;     // [NB] (rows > j)
   double *norms;  // [N]  current column norms (udv)
+  double *nuout;  // [1]  largest squared norm outside the panel at its start (udv)
   double *npart;  // [4][CW] per-wave partial norms (aliases the spare partials of Wp)
   int *orig;      // [N]  original index of each physical column (udv)
   int *sel;       // [N + 3 NB + 1] scratch for the panel selection
@@ -92,6 +82,7 @@ __device__ Lds carve(char *base, int N) {
   s.pn = p; p += S::NB;
   s.pg = p; p += S::NB;
   s.norms = p; p += N;
+  s.nuout = p; p += 1;
   s.npart = s.Wp + S::NB * S::CW;   // partial 1..3 of Wp are free once W is summed
   s.orig = (int *)p;
   s.sel = s.orig + N;
@@ -101,7 +92,7 @@ __device__ Lds carve(char *base, int N) {
 template <class S>
 size_t lds_bytes(int N) {
   const int mr = (N + 15) & ~15;
-  const size_t d = (size_t)mr * S::LDV + 4 * S::NB * S::CW + S::NB * S::CW + S::NB * S::NB + 4 * S::NB + 64 + N;
+  const size_t d = (size_t)mr * S::LDV + 4 * S::NB * S::CW + S::NB * S::CW + S::NB * S::NB + 4 * S::NB + 64 + N + 1;
   return d * sizeof(double) + sizeof(int) * (2 * N + 3 * S::NB + 1);
 }
 
@@ -134,16 +125,21 @@ __device__ __forceinline__ double sum8(double v) {
 }
 
 // Unblocked Householder on the LDS panel V[0..m) x [0..w): on return the
-// strict lower part holds v (v_j = 1 implicit), beta[j] = R_jj, tau[j].
-// Eight threads own each column.  With PIVOT the panel's columns are also
-// pivoted (largest remaining norm first, Businger-Golub within the panel);
-// the owners recompute their column's norm while applying each reflector,
-// and the swaps are recorded in swp[j] for the rows above the panel.
+// strict lower part of the first weff columns holds v (v_j = 1 implicit),
+// beta[j] = R_jj, tau[j]; the function returns weff.  Eight threads own each
+// column.  With PIVOT the panel's columns are also pivoted (largest remaining
+// norm first); the owners recompute their column's norm while applying each
+// reflector, and the swaps are recorded in swp[j] for the rows above the
+// panel.  The panel ends early (weff < w) at the first step whose best
+// in-panel norm is below nuout, the largest norm outside the panel at its
+// start: from there an outside column might be the larger.  Columns
+// [weff, w) then hold the remaining rows updated by the weff reflectors, and
+// pn[q] their squared norms over rows >= weff.
 // Reflector j is formed on the fly (x_r times its scale) where it is used
 // and stored once after the panel, so a column step needs one barrier (two
 // with pivoting); the stored values are the same products.
 template <class S, bool PIVOT>
-__device__ __forceinline__ void panel_factor(const Lds &s, int m, int w, int *swp) {
+__device__ __forceinline__ int panel_factor(const Lds &s, int m, int w, int *swp) {
   constexpr int LDV = S::LDV;
   const int t = threadIdx.x, sub = t & 7, qo = t >> 3;
   double *scl = s.red;   // [w] scale of each reflector column, applied after the panel
@@ -158,6 +154,7 @@ __device__ __forceinline__ void panel_factor(const Lds &s, int m, int w, int *sw
     if (q < w && sub == 0) { s.pn[q] = a0; s.pg[q] = a1; }
     __syncthreads();
   }
+  int weff = w;
   for (int j = 0; j < w; ++j) {
     // pivot: every wavefront finds the first column of largest norm among
     // j..w-1 (lane q holds column j + q; w <= 64; a NaN norm ranks last, so
@@ -180,6 +177,8 @@ __device__ __forceinline__ void panel_factor(const Lds &s, int m, int w, int *sw
       take(dpp_dbl<DPP_MIRROR>(best), dpp_int<DPP_MIRROR>(p));
       take(__shfl_xor(best, 16, 64), __shfl_xor(p, 16, 64));
       take(__shfl_xor(best, 32, 64), __shfl_xor(p, 32, 64));
+      // every lane of every wavefront holds the same best: the exit is uniform
+      if (j > 0 && best < s.nuout[0]) { weff = j; break; }
       if (p != j) {
         for (int r = t; r < m; r += QT) {
           const double a = s.V[r * LDV + j];
@@ -243,25 +242,28 @@ __device__ __forceinline__ void panel_factor(const Lds &s, int m, int w, int *sw
   // store the reflectors: v_r = x_r * scale below the diagonal
   for (int e = t; e < m * w; e += QT) {
     const int r = e / w, jj = e % w;
-    if (r > jj) s.V[r * LDV + jj] *= scl[jj];
+    if (r > jj && jj < weff) s.V[r * LDV + jj] *= scl[jj];
   }
   __syncthreads();
+  return weff;
 }
 
-// Write the factored panel to global (R on and above the diagonal, v below)
-// and turn LDS V into the clean reflector block (1 on the diagonal, zeros
-// above and in the padding up to mr x NB).
+// Write the panel to global (factored columns q < weff: R on and above the
+// diagonal, v below; columns [weff, w): their updated values) and turn LDS V
+// into the clean reflector block of the weff factored columns (1 on the
+// diagonal, zeros above and in the padding up to mr x NB).
 template <class S>
-__device__ __forceinline__ void panel_store_clean(const Lds &s, double *A, int N, int c0, int m, int w, int mr) {
+__device__ __forceinline__ void panel_store_clean(const Lds &s, double *A, int N, int c0, int m, int w, int weff,
+                                                  int mr) {
   constexpr int LDV = S::LDV;
   for (int e = threadIdx.x; e < m * w; e += QT) {
     const int r = e / w, q = e % w;
-    A[(long)(c0 + r) * N + c0 + q] = (r == q) ? s.beta[q] : s.V[r * LDV + q];
+    A[(long)(c0 + r) * N + c0 + q] = (r == q && q < weff) ? s.beta[q] : s.V[r * LDV + q];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < mr * S::NB; e += QT) {
     const int r = e / S::NB, q = e % S::NB;
-    const double v = (q >= w || r >= m || r < q) ? 0.0 : (r == q ? 1.0 : s.V[r * LDV + q]);
+    const double v = (q >= weff || r >= m || r < q) ? 0.0 : (r == q ? 1.0 : s.V[r * LDV + q]);
     s.V[r * LDV + q] = v;
   }
   __syncthreads();
@@ -592,6 +594,7 @@ __device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int
   int *nmv = mv_to + S::NB;
   // a NaN norm ranks last, so that the comparison stays a strict total order
   // and the ranks of the remaining columns are a permutation of 0..N-c0-1
+  if (t == 0) s.nuout[0] = 0.0;   // no column outside the panel
   for (int q = c0 + t; q < N; q += QT) {
     const double nq = isnan(s.norms[q]) ? -1.0 : s.norms[q];
     int r = 0;
@@ -605,6 +608,7 @@ __device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int
   for (int q = c0 + t; q < N; q += QT) {
     const int r = rank[q];
     if (r < w) src[r] = q;
+    if (r == w) s.nuout[0] = isnan(s.norms[q]) ? 0.0 : s.norms[q];   // largest norm left outside
     if (r < w && q >= c0 + w) {          // vacated position: k-th among them
       int k = 0;
       for (int p = c0 + w; p < q; ++p) k += rank[p] < w;
@@ -657,14 +661,17 @@ __device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int
   __syncthreads();
 }
 
-// factor A (N x N, in place) panel by panel; T of panel p saved to Tsave.
-// PIVOT: panel selection by current norms (udv).  B: reflectors also applied
-// to B's nrhs columns (solve).
+// factor A (N x N, in place) panel by panel.  Panel k's T (w_k x w_k,
+// packed) is saved to Tsave at the sum of the earlier w_j^2, and with PIVOT
+// its start and width to plist[2k], plist[2k + 1] (panels have variable
+// width there).  B: reflectors also applied to B's nrhs columns (solve).
+// Returns the number of panels.
 template <class S, bool PIVOT>
-__device__ __forceinline__ void factor(const Lds &s, double *A, double *Tsave, double *scratch, int N, double *B, int nrhs) {
+__device__ __forceinline__ int factor(const Lds &s, double *A, double *Tsave, int *plist, int N, double *B, int nrhs) {
   constexpr int NB = S::NB, LDV = S::LDV;
-  QR_TICK_INIT;
-  for (int c0 = 0; c0 < N; c0 += NB) {
+  int c0 = 0, np = 0;
+  long toff = 0;
+  while (c0 < N) {
     const int w = min(NB, N - c0), m = N - c0, mr = round16(m);
     if (PIVOT) {
       select_panel<S>(s, A, N, c0, w, m, mr);   // leaves the panel in V
@@ -677,22 +684,22 @@ __device__ __forceinline__ void factor(const Lds &s, double *A, double *Tsave, d
       }
       __syncthreads();
     }
-    QR_TICK(0);
-    QR_TICK(1);
-    panel_factor<S, PIVOT>(s, m, w, s.sel);
+    const int weff = panel_factor<S, PIVOT>(s, m, w, s.sel);
     if (PIVOT) {
       // the in-panel swaps also permute the R rows above the panel and orig[]:
       // as one gather per row, column q of the result from column idx[q]
       int *idx = s.sel + NB;
       if (threadIdx.x == 0) {
         for (int q = 0; q < w; ++q) idx[q] = q;
-        for (int j = 0; j < w; ++j) {
+        for (int j = 0; j < weff; ++j) {
           const int p = s.sel[j];
           if (p != j) {
             const int a = idx[j]; idx[j] = idx[p]; idx[p] = a;
             const int o = s.orig[c0 + j]; s.orig[c0 + j] = s.orig[c0 + p]; s.orig[c0 + p] = o;
           }
         }
+        plist[2 * np] = c0;
+        plist[2 * np + 1] = weff;
       }
       __syncthreads();
       for (int r = threadIdx.x; r < c0; r += QT) {
@@ -704,19 +711,21 @@ __device__ __forceinline__ void factor(const Lds &s, double *A, double *Tsave, d
         for (int q = 0; q < NB; ++q)
           if (q < w) A[(long)r * N + c0 + q] = v[q];
       }
+      // the panel's unfactored columns rejoin the trailing matrix with their
+      // norms over rows >= c0 + weff
+      for (int q = weff + threadIdx.x; q < w; q += QT) s.norms[c0 + q] = s.pn[q];
       __syncthreads();
     }
-    QR_TICK(2);
-    panel_store_clean<S>(s, A, N, c0, m, w, mr);
-    QR_TICK(3);
-    build_T<S>(s, m, w, mr);
-    for (int e = threadIdx.x; e < NB * NB; e += QT) Tsave[(long)(c0 / NB) * NB * NB + e] = s.T[e];
-    QR_TICK(4);
-    if (c0 + w < N) apply<S, true, PIVOT>(s, A, N, c0, m, mr, c0 + w, N, w);
-    QR_TICK(5);
+    panel_store_clean<S>(s, A, N, c0, m, w, weff, mr);
+    build_T<S>(s, m, weff, mr);
+    for (int e = threadIdx.x; e < weff * weff; e += QT) Tsave[toff + e] = s.T[(e / weff) * NB + e % weff];
+    if (c0 + w < N) apply<S, true, PIVOT>(s, A, N, c0, m, mr, c0 + w, N, weff);
     if (B) apply<S, true, false>(s, B, nrhs, c0, m, mr, 0, nrhs, 0);
-    QR_TICK(6);
+    toff += (long)weff * weff;
+    c0 += weff;
+    ++np;
   }
+  return np;
 }
 
 template <class S>
@@ -726,10 +735,10 @@ __global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long 
   const Lds s = carve<S>((char *)smem, N);
   const long NN = (long)N * N, b = blockIdx.x;
   double *X = Xall + b * NN, *U = Uall + b * NN, *RP = RPall + b * NN, *D = Dall + b * N;
-  double *Ts = Tall + b * tstride, *scr = Sall + b * (long)N * 32;
+  double *Ts = Tall + b * tstride;
+  int *plist = (int *)(Sall + b * (long)N);   // qr_scratch_doubles(N) per matrix
   const int t = threadIdx.x;
   {
-    QR_TICK_INIT;
     for (int q = t; q < N; q += QT) {
       // sixteen rows' loads in flight per step; the sum keeps the row order
       double acc = 0.0;
@@ -746,9 +755,8 @@ __global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long 
       s.orig[q] = q;
     }
     __syncthreads();   // the panel selection reads every column's norm
-    QR_TICK(9);
   }
-  factor<S, true>(s, X, Ts, scr, N, nullptr, 0);
+  const int np = factor<S, true>(s, X, Ts, plist, N, nullptr, 0);
   // D = diag R,  RP[i][orig[q]] = R[i][q] / R[i][i]
   for (int i = t; i < N; i += QT) D[i] = X[(long)i * N + i];
   // eight elements' loads in flight per step
@@ -777,16 +785,18 @@ __global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long 
   // Q = Q_0 Q_1 ... applied in reverse order to the identity
   for (long e = t; e < NN; e += QT) U[e] = ((e / N) == (e % N)) ? 1.0 : 0.0;
   __syncthreads();
-  const int np = (N + S::NB - 1) / S::NB;
-  QR_TICK_INIT;
+  long toff = 0;
+  for (int p = 0; p < np; ++p) toff += (long)plist[2 * p + 1] * plist[2 * p + 1];
   for (int p = np - 1; p >= 0; --p) {
-    const int c0 = p * S::NB, w = min(S::NB, N - c0), m = N - c0, mr = round16(m);
+    const int c0 = plist[2 * p], w = plist[2 * p + 1], m = N - c0, mr = round16(m);
+    toff -= (long)w * w;
     panel_load_clean<S>(s, X, N, c0, m, w, mr);
-    for (int e = t; e < S::NB * S::NB; e += QT) s.T[e] = Ts[(long)p * S::NB * S::NB + e];
+    for (int e = t; e < S::NB * S::NB; e += QT) {
+      const int i = e / S::NB, q = e % S::NB;
+      s.T[e] = (i < w && q < w) ? Ts[toff + i * w + q] : 0.0;
+    }
     __syncthreads();
-    QR_TICK(7);
     apply<S, false, false>(s, U, N, c0, m, mr, c0, N, 0);
-    QR_TICK(8);
   }
 }
 
@@ -888,7 +898,8 @@ size_t qr_tsave_doubles(int N) {
   return (size_t)((N + nb - 1) / nb) * nb * nb;
 }
 
-size_t qr_scratch_doubles(int N) { return (size_t)N * 32; }
+// the panel list of the pivoted factorisation: up to N panels of two ints
+size_t qr_scratch_doubles(int N) { return (size_t)N; }
 
 hipError_t qr_udv_blocked(double *X, double *Scr, double *Tsave, double *U, double *D, double *RP, int mats, int N,
                           hipStream_t s) {

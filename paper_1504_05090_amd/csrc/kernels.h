@@ -27,8 +27,9 @@ struct ChainStats {
   double logw;
   double drift_max, drift_sum;           // max_ij |G_wrapped - G_fresh|
   double rdrift_max, rdrift_sum;         // the same over max(1, max_ij |G_fresh|)
+  double rdrift_sweep;                   // largest relative drift of the current sweep
   int64_t drift_count;
-  int32_t sign, pad;
+  int32_t negs, pad;                     // accepted ratios that were negative
 };
 
 // Flip phase of one slice for every chain of one instance.
@@ -105,13 +106,16 @@ hipError_t fresh_prep(const double *UR, const double *DR, const double *VR, doub
                       const double *W2, const double *DL, double *RHS, int mats, int N,
                       hipStream_t s);
 // drift = max |G_cmp - Gf| per chain; G_out <- Gf (rounded to G_out's type);
-// cmp64 / out64 select FP64 or FP32 for G_cmp / G_out.  Each chain is split
+// cmp64 / out64 select FP64 or FP32 for G_cmp / G_out.  count: 0 leaves the
+// statistics alone, 1 adds the drift to them, 2 also starts a new sweep's
+// rdrift_sweep with it (the sweep's first recomputation).  drift_abort > 0:
+// a relative drift above it sets err bit 2.  Each chain is split
 // over DRIFT_PARTS workgroups whose maxima go to part (chains * DRIFT_PARTS * 3
 // doubles of scratch) before one wavefront per chain reduces them.
 constexpr int DRIFT_PARTS = 16;
 hipError_t drift_replace(const void *Gcmp, bool cmp64, void *Gout, bool out64, const double *Gf,
                          int chains, int N, double *part, ChainStats *stats, int *err, double drift_abort,
-                         bool count, hipStream_t s);
+                         int count, hipStream_t s);
 // dst <- src between FP64 and FP32 Green-function stacks (n elements)
 hipError_t convert_green(const void *src, bool src64, void *dst, bool dst64, long n, hipStream_t s);
 // RHS = Ds_R V_R (right-hand side of the time-displaced G(tau_l, 0) system)

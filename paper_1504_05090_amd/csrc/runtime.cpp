@@ -55,6 +55,9 @@ struct Shard {
   // parameters
   int L = 0, N = 0, Lam = 0, C = 0, mats = 0, k = 1, n_stab = 1, nb = 1;
   int m32 = 0;                           // FP32 slices at the end of each block (mixed mode)
+  int m32_max = 0;                       // automatic count, the controller's ceiling
+  bool adapt = false;                    // mixed mode, automatic count: adjusted after every sweep
+  int64_t slices_run = 0, fp32_run = 0;  // slices swept since the last statistics reset, in FP32
   int inst = 0, chain0 = 0, Ctot = 0;
   double U = 0, t = 0, beta = 0, dtau = 0, lambda = 0;
   uint64_t seed = 0;
@@ -133,8 +136,13 @@ struct bss_ctx {
   };
   std::vector<Fam> fam;
   std::vector<hipEvent_t> pool;
-  // one captured (unmeasured) sweep in two parts, replayed by bss_sweep
-  hipGraphExec_t sweep_graph[2] = {nullptr, nullptr};
+  // captured (unmeasured) sweeps, two graphs each, keyed by the FP32 slice
+  // counts of the shards they were captured with; replayed by bss_sweep
+  struct SweepGraph {
+    std::vector<int> key;
+    hipGraphExec_t g[2] = {nullptr, nullptr};
+  };
+  std::vector<SweepGraph> gcache;
   bool graphs = false;   // capture and replay sweeps (off: NO_GRAPH, PROFILE, or capture failed)
 };
 
@@ -200,11 +208,12 @@ bool valid_instance(const bss_instance &in, std::string &why, bss_status &code) 
 
 // automatic delay depth and stabilisation interval
 int auto_k(int N) { return N <= 16 ? 1 : (N <= 64 ? 16 : 32); }
-int auto_nstab(double U, double dtau) {
+int auto_nstab(double U, double t, double dtau) {
   // keep the plain FP64 block product of n slices well conditioned:
-  // cond(B) ~ e^{2 lambda + 8 t dtau}; aim at a product condition of ~1e8
+  // cond(B) = e^{2 lambda} cond(e^{-dtau K}) with cond(e^{-dtau K}) = e^{8 t dtau}
+  // (hopping spectrum [-4t, 4t]); aim at a product condition of ~1e8
   const double lam = std::acosh(std::exp(0.5 * dtau * U));
-  const double per = 2.0 * lam + 2.0 * dtau;  // log cond of one slice, t = 0.25
+  const double per = 2.0 * lam + 8.0 * t * dtau;   // log cond of one slice
   int n = (int)std::floor(std::log(1e8) / std::max(per, 1e-3));
   return std::max(1, std::min(n, 10));
 }
@@ -298,11 +307,19 @@ bool resolve(const bss_instance *in, int n, const bss_options &opt, std::vector<
     I.Ctot = in[i].n_chains; I.seed = in[i].seed; I.inst = i;
     I.lambda = std::acosh(std::exp(0.5 * I.dtau * I.U));
     I.k = opt.delay_k > 0 ? opt.delay_k : auto_k(I.N);
-    I.n_stab = opt.n_stab > 0 ? opt.n_stab : auto_nstab(I.U, I.dtau);
+    I.n_stab = opt.n_stab > 0 ? opt.n_stab : auto_nstab(I.U, I.t, I.dtau);
     I.n_stab = std::min(I.n_stab, I.Lam);
     I.nb = (I.Lam + I.n_stab - 1) / I.n_stab;
-    if (opt.precision == BSS_PREC_MIXED)
-      I.m32 = opt.fp32_slices > 0 ? std::min(opt.fp32_slices, I.n_stab) : auto_fp32_slices(I.lambda, I.n_stab);
+    if (opt.precision == BSS_PREC_MIXED) {
+      if (opt.fp32_slices > 0) {
+        I.m32 = I.m32_max = std::min(opt.fp32_slices, I.n_stab);
+      } else {
+        // automatic: start in FP64, the drift controller raises the count
+        I.m32_max = auto_fp32_slices(I.lambda, I.n_stab);
+        I.m32 = 0;
+        I.adapt = I.m32_max > 0;
+      }
+    }
     UInst U;
     U.first = (int)out.size();
     U.C = I.Ctot; U.N = I.N; U.Lam = I.Lam;
@@ -332,6 +349,7 @@ bool check_options(const bss_options *o, std::string &why) {
   if (o->trace_sweeps < 0) { why = "trace_sweeps must be >= 0"; return false; }
   if (o->fp32_slices < 0) { why = "fp32_slices must be >= 0"; return false; }
   if (!(o->drift_abort >= 0.0)) { why = "drift_abort must be >= 0"; return false; }
+  if (!(o->fp32_drift_target >= 0.0)) { why = "fp32_drift_target must be >= 0"; return false; }
   return true;
 }
 
@@ -393,7 +411,7 @@ struct Exec {
   }
   // fresh G from Gf into the precision of slice `next`, with the drift
   // against the current G recorded when `count`
-  void replace(int next, bool count, double abort_at) {
+  void replace(int next, int count, double abort_at) {
     const bool out64 = !fp32_at(next);
     Timed tm(c, F_DRIFT, s);
     chk(drift_replace(Gcur(), I.cur64, out64 ? (void *)I.G64 : (void *)I.G32, out64, I.Gf, I.C, I.N, I.dpart, I.stats,
@@ -510,7 +528,7 @@ struct Exec {
       right_update(b);
     }
     fresh(I.nb - 1, false, I.Gf);
-    replace(I.slice, false, 0.0);
+    replace(I.slice, 0, 0.0);
     left_rebuild();
     I.left_stale = false;
   }
@@ -587,7 +605,7 @@ struct Exec {
     block_product(b);
     right_update(b);
     fresh(b, false, I.Gf);
-    replace(l == I.Lam ? 1 : l + 1, true, c->opt.drift_abort);
+    replace(l == I.Lam ? 1 : l + 1, b == 0 ? 2 : 1, c->opt.drift_abort);
   }
 
   void slice(int l) {
@@ -782,6 +800,7 @@ void bss_options_default(bss_options *o) {
   std::memset(o, 0, sizeof(*o));
   o->struct_size = sizeof(bss_options);
   o->precision = BSS_PREC_FP64;
+  o->drift_abort = 0.1;
 }
 
 bss_status bss_create(int32_t L, double U, double t, double beta, double dtau, uint64_t seed, int32_t n_chains,
@@ -895,7 +914,7 @@ bool capture_range(bss_ctx *c, int l_from, int l_to, hipGraphExec_t *out) {
 // so that form is not captured.  Measured sweeps always launch directly.
 // Returns false if the runtime refuses a capture; the caller then stays with
 // direct launches.
-bool capture_sweep(bss_ctx *c) {
+bool capture_sweep(bss_ctx *c, hipGraphExec_t out[2]) {
   const size_t n = c->sh.size();
   std::vector<bool> pend(n), cur(n), stale(n);
   int l_first = 1 << 30, lam_max = 0;
@@ -927,9 +946,97 @@ bool capture_sweep(bss_ctx *c) {
     if (gb) hipGraphExecDestroy(gb);
     return false;
   }
-  c->sweep_graph[0] = ga;
-  c->sweep_graph[1] = gb;
+  out[0] = ga;
+  out[1] = gb;
   return true;
+}
+
+std::vector<int> fp32_key(const bss_ctx *c) {
+  std::vector<int> k;
+  for (auto &I : c->sh) k.push_back(I.m32);
+  return k;
+}
+
+void destroy_graphs(bss_ctx *c) {
+  for (auto &sg : c->gcache)
+    for (auto g : sg.g)
+      if (g) hipGraphExecDestroy(g);
+  c->gcache.clear();
+}
+
+// the captured sweep of the current FP32 slice counts (captured on first
+// use; at most 8 kept); nullptr if the runtime refuses the capture, after
+// which the context launches directly
+const bss_ctx::SweepGraph *sweep_graph(bss_ctx *c) {
+  const std::vector<int> key = fp32_key(c);
+  for (auto &sg : c->gcache)
+    if (sg.key == key) return &sg;
+  if (c->gcache.size() >= 8) {
+    for (auto g : c->gcache.front().g)
+      if (g) hipGraphExecDestroy(g);
+    c->gcache.erase(c->gcache.begin());
+  }
+  bss_ctx::SweepGraph sg;
+  sg.key = key;
+  if (!capture_sweep(c, sg.g)) {
+    c->graphs = false;
+    return nullptr;
+  }
+  c->gcache.push_back(sg);
+  return &c->gcache.back();
+}
+
+int64_t x_negs(const std::vector<ChainStats> &cs) {
+  int64_t n = 0;
+  for (auto &x : cs) n += x.negs;
+  return n;
+}
+
+int fp32_count(const Shard &I) {
+  int n = 0;
+  for (int l = 1; l <= I.Lam; ++l) n += fp32_slice(I, l) ? 1 : 0;
+  return n;
+}
+
+// Drift controller of mixed precision with the automatic FP32 slice count.
+// After a sweep, the largest relative wrap drift d of each adapting
+// instance's chains in that sweep moves the next sweep's count by one: down
+// if d > target / 2; up (to at most the automatic count) if d e^{2 lambda}
+// < target / 2, e^{2 lambda} being the growth one more FP32 slice brings
+// (the spread of a slice's diagonal factors amplifies an earlier rounding
+// error once per wrap).  G is then converted to the precision slice 1 needs.
+bss_status adapt_fp32(bss_ctx *c) {
+  bool any = false;
+  for (auto &I : c->sh) any = any || I.adapt;
+  if (!any) return BSS_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const double target = c->opt.fp32_drift_target > 0.0 ? c->opt.fp32_drift_target : 1e-3;
+  bool changed = false;
+  std::vector<int> next(c->sh.size());
+  for (size_t k = 0; k < c->sh.size(); ++k) {
+    Shard &I = c->sh[k];
+    next[k] = I.m32;
+    if (!I.adapt) continue;
+    std::vector<ChainStats> cs(I.C);
+    HIP_TRY(c, hipMemcpy(cs.data(), I.stats, sizeof(ChainStats) * I.C, hipMemcpyDeviceToHost));
+    double d = 0.0;
+    for (auto &x : cs) d = std::isnan(x.rdrift_sweep) ? INFINITY : std::max(d, x.rdrift_sweep);
+    if (d > 0.5 * target) next[k] = std::max(0, I.m32 - 1);
+    else if (d * std::exp(2.0 * I.lambda) < 0.5 * target) next[k] = std::min(I.m32_max, I.m32 + 1);
+    changed = changed || next[k] != I.m32;
+  }
+  if (!changed) return BSS_OK;
+  HIP_TRY(c, fork(c));
+  for (size_t k = 0; k < c->sh.size(); ++k) {
+    Shard &I = c->sh[k];
+    if (next[k] == I.m32) continue;
+    I.m32 = next[k];
+    Exec x(c, I);
+    x.use_precision(1);
+    if (x.e != hipSuccess) return exec_failed(c, x);
+  }
+  HIP_TRY(c, join(c));
+  return BSS_OK;
 }
 
 }  // namespace
@@ -942,25 +1049,36 @@ bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure) {
   if (n_sweeps < 0) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be >= 0");
   for (auto &I : c->sh)
     if (I.slice != 1) return fail(c, BSS_E_STATE, "an instance is part-way through a sweep");
-  if (n_sweeps == 0) return BSS_OK;
-  const bool replay = c->graphs && !measure;
-  if (replay && !c->sweep_graph[0] && !capture_sweep(c)) c->graphs = false;
-  if (replay && c->graphs) {
-    for (int sw = 0; sw < n_sweeps; ++sw) {
-      HIP_TRY(c, hipGraphLaunch(c->sweep_graph[0], c->stream));
-      HIP_TRY(c, hipGraphLaunch(c->sweep_graph[1], c->stream));
+  bool adapt = false;
+  for (auto &I : c->sh) adapt = adapt || I.adapt;
+  // with the drift controller the FP32 slice counts may change after every
+  // sweep, so sweeps are issued one at a time
+  const int per = adapt ? 1 : std::max(1, n_sweeps);
+  for (int done = 0; done < n_sweeps; done += per) {
+    const int n = std::min(per, n_sweeps - done);
+    const bss_ctx::SweepGraph *sg = (c->graphs && !measure) ? sweep_graph(c) : nullptr;
+    if (sg) {
+      for (int sw = 0; sw < n; ++sw) {
+        HIP_TRY(c, hipGraphLaunch(sg->g[0], c->stream));
+        HIP_TRY(c, hipGraphLaunch(sg->g[1], c->stream));
+      }
+      // the replays leave what direct launches would: slice 1 in its
+      // precision, every left rebuild waited for on the context stream
+      for (auto &I : c->sh) {
+        I.cur64 = !fp32_slice(I, 1);
+        I.left_pending = false;
+        I.left_stale = true;
+      }
+    } else if ((st = enqueue_sweeps(c, n, measure != 0)) != BSS_OK) {
+      return st;
     }
-    // the replays leave what direct launches would: slice 1 in its
-    // precision, every left rebuild waited for on the context stream
     for (auto &I : c->sh) {
-      I.cur64 = !fp32_slice(I, 1);
-      I.left_pending = false;
-      I.left_stale = true;
+      I.sweeps += n;
+      I.slices_run += (int64_t)n * I.Lam;
+      I.fp32_run += (int64_t)n * fp32_count(I);
     }
-  } else if ((st = enqueue_sweeps(c, n_sweeps, measure != 0)) != BSS_OK) {
-    return st;
+    if (adapt && (st = adapt_fp32(c)) != BSS_OK) return st;
   }
-  for (auto &I : c->sh) I.sweeps += n_sweeps;
   return BSS_OK;
 }
 
@@ -976,6 +1094,8 @@ bss_status bss_step_slices(bss_ctx *c, int32_t n_slices) {
   for (int n = 0; n < n_slices; ++n)
     for (auto &x : xs) {
       Shard &I = x.I;
+      I.slices_run += 1;
+      I.fp32_run += fp32_slice(I, I.slice) ? 1 : 0;
       x.slice(I.slice);
       if (I.slice == I.Lam) {
         x.end_of_sweep();
@@ -1034,6 +1154,25 @@ bss_status bss_get_green(bss_ctx *c, int32_t inst, int32_t chain, int32_t spin, 
   return BSS_OK;
 }
 
+bss_status bss_debug_set_green(bss_ctx *c, int32_t inst, int32_t chain, int32_t spin, int32_t i, int32_t j,
+                               double value) {
+  UInst *U;
+  bss_status st = pick(c, inst, &U);
+  if (st != BSS_OK) return st;
+  if (chain < 0 || chain >= U->C || (spin != 0 && spin != 1) || i < 0 || i >= U->N || j < 0 || j >= U->N)
+    return fail(c, BSS_E_INVALID_ARG, "bad chain/spin/indices");
+  if ((st = check_err(c)) != BSS_OK) return st;
+  Shard &I = shard_of(c, *U, chain);
+  const size_t off = (size_t)(2 * (chain - I.chain0) + spin) * nn(I) + (size_t)i * I.N + j;
+  if (I.cur64) {
+    HIP_TRY(c, hipMemcpy(I.G64 + off, &value, sizeof(double), hipMemcpyHostToDevice));
+  } else {
+    const float v = (float)value;
+    HIP_TRY(c, hipMemcpy(I.G32 + off, &v, sizeof(float), hipMemcpyHostToDevice));
+  }
+  return BSS_OK;
+}
+
 bss_status bss_get_field(bss_ctx *c, int32_t inst, int32_t chain, int8_t *out) {
   UInst *U;
   bss_status st = pick(c, inst, &U);
@@ -1082,11 +1221,7 @@ bss_status bss_set_trace(bss_ctx *c, int32_t inst, const uint8_t *accept, int32_
   HIP_TRY(c, hipMemcpy(U->trace_base, &base, sizeof(base), hipMemcpyHostToDevice));
   U->trace_cap = n_sweeps;   // sweeping past this window is an error
   // the flip launches carry the window length: captured sweeps are stale
-  for (auto &g : c->sweep_graph)
-    if (g) {
-      hipGraphExecDestroy(g);
-      g = nullptr;
-    }
+  destroy_graphs(c);
   return BSS_OK;
 }
 
@@ -1111,7 +1246,7 @@ bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
   std::memset(out, 0, sizeof(*out));
   out->sign = 1;
   double dsum = 0, rsum = 0;
-  int64_t dcnt = 0;
+  int64_t dcnt = 0, run = 0, run32 = 0, negs = 0;
   for (int k = 0; k < U->count; ++k) {
     const Shard &I = c->sh[U->first + k];
     std::vector<ChainStats> cs(I.C);
@@ -1129,10 +1264,15 @@ bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
     out->sweeps = I.sweeps;
     out->N = I.N; out->Lambda = I.Lam; out->delay_k = I.k; out->n_stab = I.n_stab;
     out->fp32_slices = I.m32;
+    run += I.slices_run;
+    run32 += I.fp32_run;
+    negs += x_negs(cs);
   }
+  out->sign = (negs % 2) ? -1 : 1;
+  out->fp32_fraction = run ? (double)run32 / (double)run : 0.0;
   out->drift_mean = dcnt ? dsum / dcnt : 0.0;
   out->drift_rel_mean = dcnt ? rsum / dcnt : 0.0;
-  out->sweep_graph = c->sweep_graph[0] ? 1 : 0;
+  out->sweep_graph = c->gcache.empty() ? 0 : 1;
   out->n_chains = U->C;
   out->shards = U->count;
   return BSS_OK;
@@ -1315,6 +1455,7 @@ bss_status bss_reset_stats(bss_ctx *c) {
     std::vector<ChainStats> zero(I.C);
     std::memset(zero.data(), 0, sizeof(ChainStats) * I.C);
     HIP_TRY(c, hipMemcpy(I.stats, zero.data(), sizeof(ChainStats) * I.C, hipMemcpyHostToDevice));
+    I.slices_run = I.fp32_run = 0;
   }
   return BSS_OK;
 }
@@ -1602,8 +1743,7 @@ void bss_destroy(bss_ctx *c) {
     for (auto &p : f.pending) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
   for (auto e : c->pool) hipEventDestroy(e);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
-  for (auto g : c->sweep_graph)
-    if (g) hipGraphExecDestroy(g);
+  destroy_graphs(c);
   if (c->own_mem && c->mem) hipFree(c->mem);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;

@@ -1,0 +1,128 @@
+"""GPU parity on the benchmark's larger configurations, through the C ABI.
+
+- the large lattices (20 x 20, beta = 40, Lambda = 80 and 100) with the
+  automatic block length: one block of the oracle's decisions replayed, G
+  compared at the block's recomputation;
+- the multigrid grid at beta = 20 (one instance per lattice side, each with
+  its automatic delay depth and block length, in one batch): one free-running
+  sweep against the oracle chain;
+- the measurement at U = 2 with several chains and measured sweeps: the
+  library's means and standard errors of G(tau_l, k) and D against the same
+  estimators formed from the oracle's per-sweep measurements of the same
+  chains.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1504_05090_amd as bss
+from paper_1504_05090_amd.workloads import BASE_SEED
+
+pytestmark = pytest.mark.gpu
+T = 0.25
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(b))))
+
+
+@pytest.mark.parametrize("U,dtau,precision,m32", [(2.0, 0.5, "fp64", 0), (2.0, 0.5, "mixed", 2),
+                                                  (1.0, 0.4, "fp64", 0)])
+def test_large_lattice_block_replay(U, dtau, precision, m32):
+    """20 x 20 (N = 400), beta = 40: the oracle's decisions for the first
+    block (automatic block length) are replayed; the field is identical bit
+    for bit and the recomputed G after the block equals the oracle's to 1e-10
+    (at the automatic block length the plain block product is conditioned to
+    about 1e8, so the oracle's G there is accurate far below 1e-10)."""
+    L, beta = 20, 40.0
+    print(f"[gpu] 20x20 beta=40 U={U} dtau={dtau} {precision} fp32_slices={m32}", flush=True)
+    g = bss.Context([dict(L=L, U=U, t=T, beta=beta, dtau=dtau, seed=BASE_SEED, n_chains=1)], precision=precision,
+                    delay_k=32, n_stab=0, flags=bss.FLAG_REPLAY_TRACE, trace_sweeps=1, fp32_slices=m32)
+    p = g.params()
+    ns, lam, N = p["n_stab"], p["Lambda"], p["N"]
+    assert lam == round(beta / dtau) and 4 <= ns <= 10
+    o = oracle.Chain(L, U, T, beta, dtau, BASE_SEED, 0, 0, ns)
+    for s in range(2):
+        assert rel(g.green(0, 0, s), o.green(s)) < 1e-10
+    tr = np.zeros(lam * N, dtype=np.uint8)
+    tr[: ns * N] = o.step_slices(ns, record=True)
+    g.set_trace(tr, 1)
+    g.step_slices(ns)
+    assert np.array_equal(g.field(), o.field())
+    for s in range(2):
+        err = rel(g.green(0, 0, s), o.green(s))
+        print(f"[gpu] n_stab={ns}, after block 1 spin {s}: rel|dG| vs oracle {err:.3e}")
+        assert err < 1e-10
+    st = g.stats()
+    print(f"[gpu] relative wrap drift {st['drift_rel_max']:.3e}, oracle {o.stats()['drift_max']:.3e}")
+    assert st["drift_rel_max"] < (1e-3 if precision == "mixed" else 1e-4)
+
+
+MULTIGRID_AT_BETA20 = [(6, 0.8), (8, 0.625), (10, 0.5), (12, 0.4)]   # (L, dtau): every side and slice width once
+
+
+def test_multigrid_grid_at_beta20():
+    """The multigrid grid's lattices at beta = 20 in one batch, automatic
+    delay depth and block length per instance: one free-running sweep of two
+    chains each follows the oracle chain (fields bit for bit, sweep-end G to
+    1e-10)."""
+    insts = [dict(L=L, U=2.0, t=T, beta=20.0, dtau=dt, seed=BASE_SEED, n_chains=2) for L, dt in MULTIGRID_AT_BETA20]
+    print("[gpu] multigrid grid at beta = 20, 4 instances x 2 chains, automatic k and n_stab", flush=True)
+    g = bss.Context(insts, precision="fp64")
+    g.sweep(1)
+    for j, (L, dt) in enumerate(MULTIGRID_AT_BETA20):
+        p = g.params(j)
+        assert p["Lambda"] == round(20.0 / dt)
+        for c in range(2):
+            o = oracle.Chain(L, 2.0, T, 20.0, dt, BASE_SEED, j, c, p["n_stab"])
+            o.sweep(1)
+            assert np.array_equal(g.field(j, c), o.field()), (j, c)
+            for s in range(2):
+                err = rel(g.green(j, c, s), o.green(s))
+                assert err < 1e-10, (j, c, s, err)
+        print(f"[gpu] L={L} dtau={dt}: k={p['delay_k']} n_stab={p['n_stab']} ok", flush=True)
+
+
+def oracle_estimates(L, U, beta, dtau, n_stab, chains, warm, meas):
+    """Per-chain means over `meas` measured sweeps (after `warm`) of D and
+    G(tau_l, k), then the library's estimators: the mean over all
+    measurements and the standard error over per-chain means."""
+    d_means, g_means = [], []
+    for c in range(chains):
+        o = oracle.Chain(L, U, T, beta, dtau, BASE_SEED, 0, c, n_stab)
+        o.sweep(warm)
+        ds, gs = [], []
+        for _ in range(meas):
+            o.sweep(1)
+            d, gk = o.measure()
+            ds.append(d)
+            gs.append(gk)
+        d_means.append(np.mean(ds))
+        g_means.append(np.mean(gs, axis=0))
+    d_means, g_means = np.array(d_means), np.array(g_means)
+    n = chains
+    return (d_means.mean(), d_means.std(ddof=1) / np.sqrt(n),
+            g_means.mean(axis=0), g_means.std(axis=0, ddof=1) / np.sqrt(n))
+
+
+@pytest.mark.parametrize("L,beta,n_stab,chains,warm,meas", [(8, 10.0, 10, 3, 1, 3), (12, 10.0, 5, 2, 0, 1)])
+def test_measurement_at_u2_against_oracle(L, beta, n_stab, chains, warm, meas):
+    """U = 2: G(tau_l, k) (stable time-displaced G through several blocks)
+    and D, their means and standard errors over chains, against the oracle's
+    per-sweep measurements of the same chains: means to 1e-10 (G) and 1e-12
+    (D), errors to 1e-9 and 1e-11."""
+    U, dtau = 2.0, 0.5
+    print(f"[gpu] measurement L={L} beta={beta} n_stab={n_stab} chains={chains} {warm}+{meas} sweeps", flush=True)
+    g = bss.Context([dict(L=L, U=U, t=T, beta=beta, dtau=dtau, seed=BASE_SEED, n_chains=chains)],
+                    precision="fp64", delay_k=16, n_stab=n_stab)
+    g.sweep(warm)
+    g.sweep(meas, measure=True)
+    d, de = g.double_occ()
+    gm, ge = g.gtau_k()
+    od, ode, ogm, oge = oracle_estimates(L, U, beta, dtau, n_stab, chains, warm, meas)
+    print(f"[gpu] D = {d:.12f} +- {de:.3e} (oracle {od:.12f} +- {ode:.3e}); "
+          f"max|dG(tau,k)| {np.max(np.abs(gm - ogm)):.3e}, max|d err| {np.max(np.abs(ge - oge)):.3e}")
+    assert abs(d - od) < 1e-12 and abs(de - ode) < 1e-11
+    assert np.max(np.abs(gm - ogm)) < 1e-10
+    assert np.max(np.abs(ge - oge)) < 1e-9
+    assert np.all(gm[1:-1] < 0)   # the paper's sign: G(tau, k) < 0 for 0 < tau < beta

@@ -1,0 +1,127 @@
+"""GPU: the numerical-failure contract and the FP32 drift controller, through
+the C ABI.
+
+Failures are forced from the host (bss_debug_set_green writes one element of
+a chain's G, as a broken Green function would hold it; a tiny drift_abort
+turns ordinary FP32 drift into a failure), so every kernel still runs to its
+end; the library must report BSS_E_NUMERICAL at the next synchronising call
+and BSS_E_STATE afterwards."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1504_05090_amd as bss
+from paper_1504_05090_amd.workloads import BASE_SEED
+
+pytestmark = pytest.mark.gpu
+T = 0.25
+
+
+def make(L=6, beta=4.0, dtau=0.5, chains=2, **kw):
+    print(f"[gpu] L={L} beta={beta} dtau={dtau} chains={chains} {kw}", flush=True)
+    return bss.Context([dict(L=L, U=2.0, t=T, beta=beta, dtau=dtau, seed=BASE_SEED, n_chains=chains)], **kw)
+
+
+def expect_failure(g, status):
+    with pytest.raises(bss.BssError) as e:
+        g.synchronize()
+    assert e.value.status == status, e.value
+    with pytest.raises(bss.BssError) as e:
+        g.stats()
+    assert e.value.status == bss.BSS_E_STATE
+
+
+@pytest.mark.parametrize("value", [float("nan"), 5.0, float("inf")], ids=["nan", "negative_ratio", "inf"])
+@pytest.mark.parametrize("precision,m32", [("fp64", 0), ("mixed", 3)])
+def test_bad_ratio_is_a_numerical_failure(value, precision, m32):
+    """A diagonal element of G that makes the site's ratio NaN, negative
+    (G_ii = 5: R_dn = 1 + (1 - 5)(e^{2 lambda} - 1) < 0) or infinite is a
+    numerical failure although the Metropolis test rejects such a proposal;
+    the oracle's reading of eq. (3) is the same (its tests force it there)."""
+    g = make(precision=precision, delay_k=4, n_stab=3, fp32_slices=m32)
+    g.synchronize()
+    g.debug_set_green(value, chain=1, spin=0, i=7, j=7)
+    g.sweep(1)
+    expect_failure(g, bss.BSS_E_NUMERICAL)
+
+
+def test_nan_off_the_diagonal_is_caught_at_the_recomputation():
+    """A NaN away from the diagonal reaches the ratios only through later
+    updates and wraps; at the latest the recomputation compares the wrapped G
+    with the fresh one and flags the non-finite difference (the maximum of a
+    NaN difference must not be dropped)."""
+    g = make(delay_k=4, n_stab=3)
+    g.synchronize()
+    g.debug_set_green(float("nan"), chain=0, spin=1, i=3, j=11)
+    g.step_slices(3)
+    expect_failure(g, bss.BSS_E_NUMERICAL)
+
+
+def test_drift_abort_on_fp32_drift():
+    """Every slice in FP32 gives a relative wrap drift far above 1e-9: with
+    drift_abort = 1e-9 the first recomputation poisons the context."""
+    g = make(precision="mixed", delay_k=4, n_stab=4, fp32_slices=4, drift_abort=1e-9)
+    g.sweep(1)
+    expect_failure(g, bss.BSS_E_NUMERICAL)
+
+
+def test_default_drift_abort_leaves_healthy_chains_alone():
+    g = make(L=8, beta=10.0, chains=4, delay_k=16, n_stab=10)
+    g.sweep(2)
+    st = g.stats()
+    assert st["sweeps"] == 2 and st["sign"] == 1 and st["drift_rel_max"] < 1e-4   # the FP64 path's ceiling
+
+
+def test_controller_raises_fp32_slices_to_the_automatic_count():
+    """Mixed precision with the automatic count: sweeps start in FP64 and the
+    controller adds one FP32 slice per sweep while the measured drift allows,
+    up to the automatic count 2 at U = 2, dtau = 0.5; the drift stays within
+    the target throughout."""
+    g = make(L=8, beta=10.0, chains=8, precision="mixed", delay_k=16, n_stab=10)
+    assert g.stats()["fp32_slices"] == 0
+    counts = []
+    for _ in range(4):
+        g.sweep(1)
+        counts.append(g.stats()["fp32_slices"])
+    st = g.stats()
+    lam = math.acosh(math.exp(0.5 * 0.5 * 2.0))
+    auto = max(0, min(10, int(math.floor(math.log(1e-5 * 2 ** 24) / (2 * lam)))))
+    print(f"[gpu] controller counts {counts}, fp32 fraction {st['fp32_fraction']:.3f}, drift {st['drift_rel_max']:.3e}")
+    assert auto == 2 and counts[:2] == [1, 2] and max(counts) == auto
+    assert 0.0 < st["fp32_fraction"] < 1.0
+    assert st["drift_rel_max"] < 1e-3
+
+
+def test_controller_with_an_unreachable_target_stays_in_fp64():
+    """A target below the FP64 drift keeps every slice in FP64, so the mixed
+    context runs the FP64 path's kernels on the same data: its chains equal
+    the FP64 context's bit for bit."""
+    kw = dict(L=6, beta=4.0, chains=3, delay_k=8, n_stab=4)
+    a = make(precision="mixed", fp32_drift_target=1e-30, **kw)
+    b = make(precision="fp64", **kw)
+    a.sweep(3)
+    b.sweep(3)
+    assert a.stats()["fp32_fraction"] == 0.0
+    for c in range(3):
+        assert np.array_equal(a.field(0, c), b.field(0, c))
+        for s in range(2):
+            assert np.array_equal(a.green(0, c, s), b.green(0, c, s))
+
+
+def test_controller_chain_matches_the_oracle():
+    """With the controller switching precisions between sweeps, the chain is
+    still the oracle's Markov chain: fields bit for bit, and the sweep-end G
+    (a fresh FP64 recomputation) to 1e-10."""
+    L, beta, dtau, n_stab = 6, 4.0, 0.5, 4
+    g = make(L=L, beta=beta, dtau=dtau, chains=2, precision="mixed", delay_k=8, n_stab=n_stab)
+    g.sweep(3)
+    assert g.stats()["fp32_fraction"] > 0.0
+    for c in range(2):
+        o = oracle.Chain(L, 2.0, T, beta, dtau, BASE_SEED, 0, c, n_stab)
+        o.sweep(3)
+        assert np.array_equal(g.field(0, c), o.field()), c
+        for s in range(2):
+            err = np.max(np.abs(g.green(0, c, s) - o.green(s))) / max(1.0, np.max(np.abs(o.green(s))))
+            assert err < 1e-10, (c, s, err)
