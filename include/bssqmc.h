@@ -294,6 +294,23 @@ typedef struct {
 bss_status bss_autotune(const bss_instance *inst, const bss_options *base, double drift_bound,
                         int32_t warmup_sweeps, int32_t trial_sweeps, bss_tune_result *out);
 
+/* Equal-time Green functions of both spins at the start of slice l
+ * (1..Lambda) for one Ising field, recomputed from scratch exactly as a sweep
+ * recomputes them every n_stab slices (eq. (3): G_sigma = M_sigma^{-1} with
+ * M_sigma = I + B_{l-1} .. B_1 B_Lambda .. B_l; UDV/QR over blocks of n_stab
+ * slices, closed after every multiple of n_stab and after Lambda, then the
+ * scale-separated inverse; FP64).  field: DEVICE int8 [Lambda][N] (+-1);
+ * G_out: DEVICE FP64 [2][N][N], spin up then down, row-major, positive
+ * convention; both caller-owned.  Model arguments as for bss_create.  The
+ * call allocates its scratch (about 20 N^2 doubles) with hipMalloc, runs on
+ * `stream` (a hipStream_t; NULL: the null stream) and returns after the work
+ * has finished and the scratch is freed.  INVALID_ARG: bad model arguments,
+ * n_stab < 1, l outside 1..Lambda, NULL pointers; UNSUPPORTED: odd L or
+ * N > 512; OUT_OF_MEMORY; DEVICE.  Entries of field other than +-1 give
+ * undefined results. */
+bss_status bss_green_from_field(int32_t L, double U, double t, double beta, double dtau, int32_t n_stab, int32_t l,
+                                const int8_t *field, double *G_out, void *stream);
+
 /* Overwrite element (i, j) of the current Green function of one chain and
  * spin (in the precision the current slice holds it) with `value`, e.g. a NaN
  * or a value outside [0, 1] on the diagonal.  For tests of the failure

@@ -26,7 +26,7 @@ EXPORTS = [
     "bss_step_slices", "bss_measure_gtau_k", "bss_measure_double_occ", "bss_reset_measurements", "bss_reset_stats", "bss_synchronize",
     "bss_get_green", "bss_get_field", "bss_set_field", "bss_set_trace", "bss_get_trace",
     "bss_get_stats", "bss_save", "bss_load", "bss_destroy", "bss_status_string", "bss_last_error",
-    "bss_get_profile", "bss_reset_profile", "bss_autotune", "bss_debug_set_green",
+    "bss_get_profile", "bss_reset_profile", "bss_autotune", "bss_debug_set_green", "bss_green_from_field",
 ]
 
 
@@ -106,6 +106,7 @@ def lib():
         L.bss_reset_profile.argtypes = [vp]
         L.bss_autotune.argtypes = [P(Instance), P(Options), dbl, i32, i32, P(TuneResult)]
         L.bss_debug_set_green.argtypes = [vp, i32, i32, i32, i32, i32, dbl]
+        L.bss_green_from_field.argtypes = [i32, dbl, dbl, dbl, dbl, i32, i32, vp, vp, vp]
         L.bss_destroy.argtypes = [vp]
         L.bss_destroy.restype = None
         L.bss_status_string.argtypes = [i32]
@@ -298,6 +299,26 @@ class Context:
     def load(self, data: bytes):
         buf = ctypes.create_string_buffer(data, len(data))
         self._check(lib().bss_load(self._h, buf, len(data)), "bss_load")
+
+
+def green_from_field(L, U, t, beta, dtau, n_stab, l, field, out=None, stream=None):
+    """bss_green_from_field: G of both spins at the start of slice l for a
+    field.  `field` is a torch int8 device tensor [Lambda, N]; `out` (optional)
+    a torch float64 device tensor [2, N, N], returned."""
+    import torch  # device memory and streams only
+
+    N = L * L
+    assert field.is_cuda and field.dtype == torch.int8 and field.is_contiguous() and field.shape[-1] == N
+    if out is None:
+        out = torch.empty((2, N, N), dtype=torch.float64, device=field.device)
+    assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() == 2 * N * N
+    s = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
+    fn = lib().bss_green_from_field
+    st = fn(int(L), float(U), float(t), float(beta), float(dtau), int(n_stab), int(l), field.data_ptr(),
+            out.data_ptr(), s)
+    if st != BSS_OK:
+        raise BssError(st, f"{fn.__name__}: {lib().bss_status_string(st).decode()}")
+    return out
 
 
 def autotune(instance: dict, precision="fp64", drift_bound=1e-6, warmup_sweeps=4, trial_sweeps=2, flags=0) -> dict:

@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbssqmc.so")
 
-SOURCES = ["k_gemm.hip", "k_hop.hip", "k_setup.hip", "k_flip.hip", "k_linalg.hip", "k_qr.hip", "k_measure.hip", "runtime.cpp"]
+SOURCES = ["k_gemm.hip", "k_hop.hip", "k_setup.hip", "k_flip.hip", "k_linalg.hip", "k_qr.hip", "k_measure.hip",
+           "green.hip", "runtime.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

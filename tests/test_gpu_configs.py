@@ -126,3 +126,54 @@ def test_measurement_at_u2_against_oracle(L, beta, n_stab, chains, warm, meas):
     assert np.max(np.abs(gm - ogm)) < 1e-10
     assert np.max(np.abs(ge - oge)) < 1e-9
     assert np.all(gm[1:-1] < 0)   # the paper's sign: G(tau, k) < 0 for 0 < tau < beta
+
+
+GOLDEN_L16 = "tests/golden/field_L16_U2_b20_dt0.5_w20.npy"
+
+
+@pytest.mark.parametrize("l", [1, 4, 10])
+def test_green_from_field_against_oracle(l):
+    """bss_green_from_field (both spins of one field, slice l, device in and
+    out) against the oracle's recomputation with the same block length."""
+    import torch
+    L, U, beta, dtau, n_stab = 6, 2.0, 4.0, 0.4, 3
+    o = oracle.Chain(L, U, T, beta, dtau, BASE_SEED, 0, 1, n_stab)
+    f = o.field()
+    print(f"[gpu] green_from_field 6x6 l={l}", flush=True)
+    G = bss.green_from_field(L, U, T, beta, dtau, n_stab, l, torch.from_numpy(f).cuda()).cpu().numpy()
+    for s in range(2):
+        assert rel(G[s], o.fresh_green(l, s, f)) < 1e-10, s
+
+
+def test_green_from_field_on_the_headline_lattice():
+    """16 x 16, beta = 20, n_stab = 8 on an equilibrated field: G at slice 1
+    equals the context's own recomputation after set_field (same kernels,
+    same blocks) and the exact G to 1e-10; at slice 9 (blocks starting
+    there) the exact G to 1e-10."""
+    import os
+    import torch
+    f = np.load(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), GOLDEN_L16))
+    print("[gpu] green_from_field 16x16 beta=20", flush=True)
+    fd = torch.from_numpy(f).cuda()
+    g1 = bss.green_from_field(16, 2.0, T, 20.0, 0.5, 8, 1, fd).cpu().numpy()
+    g9 = bss.green_from_field(16, 2.0, T, 20.0, 0.5, 8, 9, fd).cpu().numpy()
+    c = bss.Context([dict(L=16, U=2.0, t=T, beta=20.0, dtau=0.5, seed=BASE_SEED, n_chains=1)], precision="fp64",
+                    delay_k=32, n_stab=8)
+    c.set_field(f)
+    ex = oracle.Chain(16, 2.0, T, 20.0, 0.5, BASE_SEED, 0, 0, 1)
+    for s in range(2):
+        e_ctx = rel(g1[s], c.green(0, 0, s))
+        e1, e9 = rel(g1[s], ex.fresh_green(1, s, f)), rel(g9[s], ex.fresh_green(9, s, f))
+        print(f"[gpu] spin {s}: vs context {e_ctx:.3e}, vs exact at l=1 {e1:.3e}, at l=9 {e9:.3e}")
+        assert e_ctx < 1e-12 and e1 < 1e-10 and e9 < 1e-10
+
+
+def test_green_from_field_argument_errors():
+    import torch
+    f = torch.ones((8, 16), dtype=torch.int8, device="cuda")
+    with pytest.raises(bss.BssError) as e:
+        bss.green_from_field(4, 2.0, T, 4.0, 0.5, 4, 0, f)          # l outside 1..Lambda
+    assert e.value.status == bss.BSS_E_INVALID_ARG
+    with pytest.raises(bss.BssError) as e:
+        bss.green_from_field(4, 2.0, T, 4.1, 0.5, 4, 1, f)          # beta / dtau not integral
+    assert e.value.status == bss.BSS_E_INVALID_ARG
