@@ -311,6 +311,21 @@ bss_status bss_autotune(const bss_instance *inst, const bss_options *base, doubl
 bss_status bss_green_from_field(int32_t L, double U, double t, double beta, double dtau, int32_t n_stab, int32_t l,
                                 const int8_t *field, double *G_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation, arguments and errors as bss_green_from_field, but the scratch
+ * is a fixed device array of the library (bss_green_from_field_noalloc_limit()
+ * bytes, 12 MiB: one 16 x 16 field at any n_stab up to several hundred), held
+ * by each device from the first call on it until the process ends.  Nothing
+ * is allocated or freed and nothing is synchronised: the call enqueues on
+ * `stream` and returns.  All calls on one device share that array, so calls
+ * that overlap on one device (different streams or host threads) race; calls
+ * in order on one stream are safe.  UNSUPPORTED also when the field's scratch
+ * would exceed the limit. */
+size_t bss_green_from_field_noalloc_limit(void);
+bss_status bss_green_from_field_noalloc(int32_t L, double U, double t, double beta, double dtau, int32_t n_stab,
+                                        int32_t l, const int8_t *field, double *G_out, void *stream);
+
 /* Overwrite element (i, j) of the current Green function of one chain and
  * spin (in the precision the current slice holds it) with `value`, e.g. a NaN
  * or a value outside [0, 1] on the diagonal.  For tests of the failure

@@ -27,6 +27,7 @@ EXPORTS = [
     "bss_get_green", "bss_get_field", "bss_set_field", "bss_set_trace", "bss_get_trace",
     "bss_get_stats", "bss_save", "bss_load", "bss_destroy", "bss_status_string", "bss_last_error",
     "bss_get_profile", "bss_reset_profile", "bss_autotune", "bss_debug_set_green", "bss_green_from_field",
+    "bss_green_from_field_noalloc", "bss_green_from_field_noalloc_limit",
 ]
 
 
@@ -107,6 +108,9 @@ def lib():
         L.bss_autotune.argtypes = [P(Instance), P(Options), dbl, i32, i32, P(TuneResult)]
         L.bss_debug_set_green.argtypes = [vp, i32, i32, i32, i32, i32, dbl]
         L.bss_green_from_field.argtypes = [i32, dbl, dbl, dbl, dbl, i32, i32, vp, vp, vp]
+        L.bss_green_from_field_noalloc.argtypes = [i32, dbl, dbl, dbl, dbl, i32, i32, vp, vp, vp]
+        L.bss_green_from_field_noalloc_limit.argtypes = []
+        L.bss_green_from_field_noalloc_limit.restype = sz
         L.bss_destroy.argtypes = [vp]
         L.bss_destroy.restype = None
         L.bss_status_string.argtypes = [i32]
@@ -115,7 +119,8 @@ def lib():
         L.bss_last_error.restype = ctypes.c_char_p
         for nm in EXPORTS:
             f = getattr(L, nm)
-            if nm not in ("bss_options_default", "bss_destroy", "bss_status_string", "bss_last_error"):
+            if nm not in ("bss_options_default", "bss_destroy", "bss_status_string", "bss_last_error",
+                          "bss_green_from_field_noalloc_limit"):
                 f.restype = i32
         _lib = L
     return _lib
@@ -301,10 +306,12 @@ class Context:
         self._check(lib().bss_load(self._h, buf, len(data)), "bss_load")
 
 
-def green_from_field(L, U, t, beta, dtau, n_stab, l, field, out=None, stream=None):
+def green_from_field(L, U, t, beta, dtau, n_stab, l, field, out=None, stream=None, noalloc=False):
     """bss_green_from_field: G of both spins at the start of slice l for a
     field.  `field` is a torch int8 device tensor [Lambda, N]; `out` (optional)
-    a torch float64 device tensor [2, N, N], returned."""
+    a torch float64 device tensor [2, N, N], returned.  noalloc: the variant
+    with the library's static scratch (bss_green_from_field_noalloc), which
+    allocates nothing and does not synchronise."""
     import torch  # device memory and streams only
 
     N = L * L
@@ -313,7 +320,7 @@ def green_from_field(L, U, t, beta, dtau, n_stab, l, field, out=None, stream=Non
         out = torch.empty((2, N, N), dtype=torch.float64, device=field.device)
     assert out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() == 2 * N * N
     s = (stream if stream is not None else torch.cuda.current_stream()).cuda_stream
-    fn = lib().bss_green_from_field
+    fn = lib().bss_green_from_field_noalloc if noalloc else lib().bss_green_from_field
     st = fn(int(L), float(U), float(t), float(beta), float(dtau), int(n_stab), int(l), field.data_ptr(),
             out.data_ptr(), s)
     if st != BSS_OK:
