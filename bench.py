@@ -5,27 +5,31 @@ dtau = 0.5, Lambda = 40) with 128 independent Markov chains, delayed updates
 of rank 32 and FP64 recomputation every 8 slices.  One step = one sweep of
 every chain (128 x 256 x 40 = 1,310,720 Ising-field updates, both spins).
 
-The headline path is mixed precision: FP32 G, flips, flushes and wraps in
-the last fp32_slices slices of every block (chosen automatically from the
-coupling, 2 at this U and dtau; an FP32 error made s wraps before a
-recomputation grows ~e^{2 lambda} per wrap), FP64 elsewhere and for all
-stabilisation.  The all-FP64 path is timed beside it, and so is the
-all-FP32-bulk variant, whose drift shows why it is not the headline.
+The headline path is mixed precision with the automatic FP32 slice count:
+FP32 G, flips, flushes and wraps in the last slices of every block, as many
+as the library's drift controller allows (an FP32 error made s wraps before a
+recomputation grows ~e^{2 lambda} per wrap; the controller starts in FP64 and
+keeps the measured relative drift below 1e-3), FP64 everywhere else and for
+all stabilisation.  The all-FP64 path is timed beside it.
 
-Prints one JSON line: updates/s of the headline path (inputs resident on the
-GPU, chains equilibrated by the warm-up sweeps), the FP64 path and the
-speedup; the relative wrap drift max|G_wrapped - G_fresh| / max(1, max|G|)
-over the timed sweeps and max|dG| of sampled chains against the FP64 oracle;
-the roofline of the dominant kernel family (HIP-event timings of the
-library's own profiler on the stream it launches on) and the MFMA fraction of
-the whole sweep; the oracle timed on the host cores.
+Prints one JSON line: updates/s of the headline path (everything resident on
+the GPU, chains equilibrated by the warm-up sweeps) and of the FP64 path, the
+relative wrap drift over the timed sweeps, the FP32 fraction, max|dG| of the
+FP32 slices against the FP64 path on one identical history, the roofline of
+the dominant kernel family in the timed configuration, the HBM rate of the
+forced rank-1 path, the multigrid batch, and (the cpu_baseline leg) the oracle
+timed on the host cores together with max|dG| of sampled sweep-end Green
+functions against the oracle's.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
+import time
 
 import numpy as np
 
@@ -36,58 +40,37 @@ METRIC = "HS field updates/sec at 16x16, β=20 (FP32+FP64-stab vs FP64), max|ΔG
 PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 HBM_PEAK = 8.0e12
 
-# HBM bytes per launch (FETCH_SIZE x 1.9998 + WRITE_SIZE x 1.0, the scales a
-# 256 MiB device copy gives) from the profiles/*hbm_traffic.md summaries of
-# each hopping mode, valid while the kernel's source file is the one the
-# counters were taken on (sha1 prefix); otherwise the traffic is reported as
-# null.
-_COMMON_TRAFFIC = {
-    "flip_f64": (1.169e9, "k_flip.hip", "217c6bae88cd"),
-    "flip_f32": (5.534e8, "k_flip.hip", "217c6bae88cd"),
-    "qr_udv": (2.775e9, "k_qr.hip", "4ca8710ab0ca"),
-    "qr_solve": (2.953e9, "k_qr.hip", "4ca8710ab0ca"),
-}
-# per launch of all 128 chains (the profile pass runs them as one shard)
+# HBM bytes per launch of one 32-chain shard (64 matrices), FETCH_SIZE x f +
+# WRITE_SIZE x w with the scales f, w a device copy of known size gives
+# (profiles/*_hbm_traffic.md), valid while the kernel's source file is the
+# one the counters were taken on (sha1 prefix); otherwise null.
 TRAFFIC = {
-    "dense": dict(_COMMON_TRAFFIC, **{
-        "wrap_f32": (1.703e8, "k_gemm.hip", "57c2c9444073"),
-        # mean over every full-size dispatch of the FP64 NN GEMM kernel (wraps,
-        # block products and UDV products share it)
-        "wrap_f64": (4.527e8, "k_gemm.hip", "57c2c9444073"),
-    }),
-    "kronecker": dict(_COMMON_TRAFFIC, **{
-        # wraps: one right and one left Kronecker-factor product each (mean of the two)
-        "wrap_f64": (2.725e8, "k_hop.hip", "990a600b01dc"),
-        "wrap_f32": (1.358e8, "k_hop.hip", "990a600b01dc"),
-        "hop_f64": (2.710e8, "k_hop.hip", "990a600b01dc"),
-    }),
+    "dense": {},
+    "kronecker": {},
 }
 
 
 def traffic_of(fam: str, hopping: str):
-    import hashlib
     if fam not in TRAFFIC[hopping]:
         return None
     val, src, sha = TRAFFIC[hopping][fam]
-    path = os.path.join(ROOT, "paper_1504_05090_amd", "csrc", src)
-    with open(path, "rb") as f:
+    with open(os.path.join(ROOT, "paper_1504_05090_amd", "csrc", src), "rb") as f:
         return val if hashlib.sha1(f.read()).hexdigest()[:12] == sha else None
 
 
-def family_model(fam: str, N: int, mats: int, chains: int, acc: float, k: int, kron: bool = False):
+def family_model(fam: str, N: int, mats: float, chains: float, acc: float, k: int, kron: bool = False):
     """Algorithmic work of one launch of a kernel family: (amount, peak per second, bound).
 
     MFMA-bound families count flops against the dense MFMA peak of their
-    dtype; the Kronecker-factor products (the wraps with kron, block and
-    measurement products) count the bytes they must move, X read and Y written
-    once, against HBM bandwidth."""
+    dtype; the Kronecker-factor products count the bytes they must move, X
+    read and Y written once, against HBM bandwidth."""
     if fam == "hop_f64" or (kron and fam in ("wrap_f32", "wrap_f64")):
         esz = 4 if fam.endswith("f32") else 8
         return 2.0 * mats * N * N * esz, HBM_PEAK, "hbm"
     if fam in ("wrap_f32", "wrap_f64", "gemm_f64"):
-        return 2.0 * N ** 3 * mats, PEAK[fam[-3:]], "mfma"     # one batched N x N x N product
+        return 2.0 * N ** 3 * mats, PEAK[fam[-3:]], "mfma"      # one batched N x N x N product
     if fam == "qr_udv":
-        return (8.0 / 3.0) * N ** 3 * mats, PEAK["f64"], "mfma"   # Householder R (4/3 N^3) + explicit Q (4/3 N^3)
+        return (8.0 / 3.0) * N ** 3 * mats, PEAK["f64"], "mfma"  # Householder R (4/3 N^3) + explicit Q (4/3 N^3)
     if fam == "qr_solve":
         return (13.0 / 3.0) * N ** 3 * mats, PEAK["f64"], "mfma"  # R (4/3), Q^T on N columns (2), back substitution (1)
     if fam in ("flip_f32", "flip_f64"):
@@ -97,36 +80,121 @@ def family_model(fam: str, N: int, mats: int, chains: int, acc: float, k: int, k
     return 0.0, None, None
 
 
-def _family_roofline(fam, entry, N, mats, chains, acc, k, kron):
-    launches, tot = entry
-    amount, peak, bound = family_model(fam, N, mats, chains, acc, k, kron)
-    if not amount or not launches:
-        return {"launches": launches, "avg_launch_ms": tot / max(1, launches)}
-    avg_ms = tot / launches
-    return {"launches": launches, "avg_launch_ms": round(avg_ms, 5), "bound": bound,
-            "frac": round(amount / (avg_ms / 1e3) / peak, 4)}
-
-
-def run_path(bss, inst, precision, k, n_stab, steps, warmup, fp32_slices=0, profile=False, flags=0):
+def timed_sweeps(ctx, stream, n, measure=False):
     import torch
-    stream = torch.cuda.Stream()
-    flags |= bss.FLAG_PROFILE if profile else 0
-    ctx = bss.Context([inst], precision=precision, delay_k=k, n_stab=n_stab, flags=flags, stream=stream,
-                      fp32_slices=fp32_slices)
-    ctx.sweep(warmup)
-    stream.synchronize()
-    ctx.reset_stats()
-    if profile:
-        ctx.reset_profile()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    ctx.sweep(steps)
+    ctx.sweep(n, measure=measure)
     e1.record(stream)
     e1.synchronize()
-    ms = e0.elapsed_time(e1)
-    st = ctx.stats()
-    prof = ctx.profile() if profile else None
-    return ctx, ms, st, prof
+    return e0.elapsed_time(e1)
+
+
+def run_path(bss, inst, precision, k, n_stab, steps, warmup, fp32_slices=0, flags=0, drift_abort=None):
+    import torch
+    stream = torch.cuda.Stream()
+    ctx = bss.Context([inst], precision=precision, delay_k=k, n_stab=n_stab, flags=flags, stream=stream,
+                      fp32_slices=fp32_slices, drift_abort=drift_abort)
+    ctx.sweep(warmup)
+    ctx.synchronize()
+    ctx.reset_stats()
+    ms = timed_sweeps(ctx, stream, steps)
+    return ctx, stream, ms, ctx.stats()
+
+
+def summary(st):
+    return {"acceptance": st["accepted"] / max(1, st["proposals"]), "drift_rel_max": st["drift_rel_max"],
+            "drift_rel_mean": st["drift_rel_mean"], "fp32_slices": st["fp32_slices"],
+            "fp32_fraction": st["fp32_fraction"], "fp32_rejected": st["fp32_rejected"],
+            "fp32_fused": st["fp32_fused"]}
+
+
+def fp32_error_on_identical_history(bss, inst, field, k, n_stab, m32, n_slices):
+    """max_ij |G_mixed - G_fp64| / max(1, max|G_fp64|) over the slices after
+    which the mixed path holds G in FP32, on one history: the FP64 path
+    records its accept decisions for n_slices slices from `field`, the mixed
+    path (FP32 in the last m32 slices of each block) replays them."""
+    one = dict(inst, n_chains=1)
+    a = bss.Context([one], precision="fp64", delay_k=k, n_stab=n_stab, flags=bss.FLAG_RECORD_TRACE, trace_sweeps=1)
+    a.set_field(field)
+    ref = []
+    for _ in range(n_slices):
+        a.step_slices(1)
+        ref.append([a.green(0, 0, s) for s in range(2)])
+    tr = a.get_trace(1)
+    b = bss.Context([one], precision="mixed", delay_k=k, n_stab=n_stab, flags=bss.FLAG_REPLAY_TRACE, trace_sweeps=1,
+                    fp32_slices=m32)
+    b.set_field(field)
+    b.set_trace(tr, 1)
+    lam = int(round(inst["beta"] / inst["dtau"]))
+
+    def fp32_slice(l):
+        return min(((l - 1) // n_stab + 1) * n_stab, lam) - l < m32
+
+    worst, same = 0.0, True
+    for l in range(1, n_slices + 1):
+        b.step_slices(1)
+        # G is held in FP32 after an FP32 slice that does not end a block, and
+        # after a recomputation that precedes an FP32 slice
+        ends_block = l % n_stab == 0 or l == lam
+        in_fp32 = fp32_slice(l + 1) if ends_block else fp32_slice(l)
+        for s in range(2):
+            g, r = b.green(0, 0, s), ref[l - 1][s]
+            if in_fp32:
+                worst = max(worst, float(np.max(np.abs(g - r)) / max(1.0, np.max(np.abs(r)))))
+            else:
+                same = same and bool(np.array_equal(g, r))
+    same = same and bool(np.array_equal(a.field(), b.field()))
+    return worst, same
+
+
+def profile_pass(bss, inst, k, n_stab, m32, ckpt, steps, flags):
+    """Per-launch HIP-event timings of every kernel family in the timed
+    configuration (same shards, the FP32 slice count the controller ended
+    on), from the timed context's checkpoint: direct launches with an event
+    pair around each launch on the stream it is issued on."""
+    import torch
+    stream = torch.cuda.Stream()
+    prec = "mixed" if m32 > 0 else "fp64"
+    ctx = bss.Context([inst], precision=prec, delay_k=k, n_stab=n_stab, flags=flags | bss.FLAG_PROFILE,
+                      stream=stream, fp32_slices=m32)
+    ctx.load(ckpt)
+    ctx.sweep(1)
+    ctx.synchronize()
+    ctx.reset_stats()
+    ctx.reset_profile()
+    ms = timed_sweeps(ctx, stream, steps)
+    st, prof = ctx.stats(), ctx.profile()
+    del ctx
+    return ms, st, prof
+
+
+def rank1_pass(bss, inst, steps):
+    """The forced rank-1 path (delay depth 1, FP64) on the same workload:
+    every accepted flip reads and writes both spins' G (32 N^2 bytes), so its
+    HBM rate is the measure of the flip kernel there."""
+    import torch
+    stream = torch.cuda.Stream()
+    ctx = bss.Context([inst], precision="fp64", delay_k=1, n_stab=8, flags=bss.FLAG_PROFILE, stream=stream)
+    ctx.sweep(2)
+    ctx.synchronize()
+    ctx.reset_stats()
+    ctx.reset_profile()
+    ms = timed_sweeps(ctx, stream, steps)
+    st, prof = ctx.stats(), ctx.profile()
+    del ctx
+    N = inst["L"] ** 2
+    acc = st["accepted"] / max(1, st["proposals"])
+    launches, tot = prof["flip_f64"]
+    chains_per_launch = inst["n_chains"] / st["shards"]
+    bytes_per_launch = chains_per_launch * acc * N * 32.0 * N * N
+    avg_s = tot / launches / 1e3
+    return {"workload": "the headline workload with delay depth 1 (rank-1 Sherman-Morrison), FP64",
+            "updates_per_s": inst["n_chains"] * N * int(round(inst["beta"] / inst["dtau"])) * steps / (ms / 1e3),
+            "acceptance": acc, "flip_avg_launch_ms": tot / launches, "flip_launches": launches,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "achieved_GBps": bytes_per_launch / avg_s / 1e9, "peak_GBps": HBM_PEAK / 1e9,
+            "frac": bytes_per_launch / avg_s / HBM_PEAK}
 
 
 def run_batch(bss, insts, steps, warmup, flags):
@@ -136,21 +204,61 @@ def run_batch(bss, insts, steps, warmup, flags):
     ctx = bss.Context(insts, precision="fp64", stream=stream, flags=flags)
     ctx.sweep(warmup)
     ctx.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    ctx.sweep(steps)
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1)
+    ms = timed_sweeps(ctx, stream, steps)
     upd = sum(d["n_chains"] * d["L"] ** 2 * int(round(d["beta"] / d["dtau"])) for d in insts)
+    params = [dict(L=insts[j]["L"], dtau=insts[j]["dtau"], **{q: ctx.params(j)[q] for q in ("delay_k", "n_stab")})
+              for j in range(len(insts))]
     graph = ctx.stats(0)["sweep_graph"]
     del ctx
-    return upd * steps / (ms / 1e3), ms / steps, graph
+    return upd * steps / (ms / 1e3), ms / steps, graph, params
 
 
-def summary(st):
-    return {"acceptance": st["accepted"] / max(1, st["proposals"]), "drift_rel_max": st["drift_rel_max"],
-            "drift_rel_mean": st["drift_rel_mean"], "fp32_slices": st["fp32_slices"]}
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline_leg(p, n_stab, ctx, C):
+    """The oracle as it stands, on the host cores: updates/s on all cores of
+    this process's share (one chain per core, 1 untimed + 1 timed sweep) and
+    on one core (1 chain, 1 timed sweep).  Then the sampled parity check of
+    the timed run's end state: sweep-end G of chains 0 and C-1 against the
+    oracle's exact G (one slice per block) and its G at the same block length."""
+    import oracle
+    from paper_1504_05090_amd.workloads import BASE_SEED, T_HOP
+    N, lam = p["L"] ** 2, int(round(p["beta"] / p["dtau"]))
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    t0 = time.time()
+    sec, used = oracle.run_chains(p["L"], p["U"], T_HOP, p["beta"], p["dtau"], BASE_SEED, cores, n_stab, 1,
+                                  cores, n_warm=1)
+    sec1, _ = oracle.run_chains(p["L"], p["U"], T_HOP, p["beta"], p["dtau"], BASE_SEED, 1, n_stab, 1, 1)
+    wall = time.time() - t0
+    cpu = {"value": cores * N * lam / sec, "unit": "updates/s", "cores": used, "kind": "oracle",
+           "value_1_core": N * lam / sec1, "cpu_model": cpu_model(),
+           "sample": f"{cores} chains x (1 untimed + 1 timed) sweep of the headline 16x16 workload, one chain "
+                     f"per core, and 1 chain x 1 timed sweep on one core (FP64 oracle: rank-1 updates, full "
+                     f"recomputation with column pivoting, gcc -O3, OpenMP over chains); {wall:.1f} s in all"}
+    ex = oracle.Chain(p["L"], p["U"], T_HOP, p["beta"], p["dtau"], BASE_SEED, 0, 0, 1)
+    same = oracle.Chain(p["L"], p["U"], T_HOP, p["beta"], p["dtau"], BASE_SEED, 0, 0, n_stab)
+    d_ex, d_same = 0.0, 0.0
+    for c in (0, C - 1):
+        f = ctx.field(0, c)
+        for s in range(2):
+            g = ctx.green(0, c, s)
+            for o, which in ((ex, "ex"), (same, "same")):
+                r = o.fresh_green(1, s, f)
+                d = float(np.max(np.abs(g - r)) / max(1.0, np.max(np.abs(r))))
+                if which == "ex":
+                    d_ex = max(d_ex, d)
+                else:
+                    d_same = max(d_same, d)
+    return cpu, d_ex, d_same
 
 
 def main():
@@ -165,9 +273,10 @@ def main():
                          "definition) or the Kronecker-factor products")
     ap.add_argument("--no-kronecker", action="store_true",
                     help="skip the Kronecker-hopping line beside a dense headline")
-    ap.add_argument("--cpu-chains", type=int, default=0, help="oracle chains for the CPU baseline (0 = cores)")
+    ap.add_argument("--all-fp32", action="store_true",
+                    help="also time every slice in FP32 (not valid at this coupling: its drift is O(1))")
     ap.add_argument("--no-batch", action="store_true", help="skip the multigrid-batch measurement")
-    ap.add_argument("--no-oracle-check", action="store_true", help="skip the sampled comparison with the oracle")
+    ap.add_argument("--no-rank1", action="store_true", help="skip the forced rank-1 (k = 1) HBM measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB between two device buffers three times (a plain copy kernel of "
                          "known size, to scale HBM byte counters)")
@@ -189,7 +298,8 @@ def main():
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"[bench] copy calibration: 3 x {args.calibrate_copy} MiB device-to-device", file=sys.stderr, flush=True)
+        print(f"[bench] copy calibration: 3 x {args.calibrate_copy} MiB device-to-device", file=sys.stderr,
+              flush=True)
         del src, dst
 
     cfg = CONFIGS["C4"]
@@ -202,95 +312,77 @@ def main():
 
     kron_head = args.hopping == "kronecker"
     hflags = bss.FLAG_KRONECKER_HOPPING if kron_head else 0
-    ctx, ms, st, _ = run_path(bss, inst, "mixed", k, n_stab, args.steps, args.warmup, flags=hflags)
+
+    # 1. the headline: mixed precision, automatic FP32 slice count
+    ctx, stream, ms, st = run_path(bss, inst, "mixed", k, n_stab, args.steps, args.warmup, flags=hflags)
     value = updates_per_step * args.steps / (ms / 1e3)
     mixed = summary(st)
     m32 = mixed["fp32_slices"]
-    print(f"[bench] mixed (FP32 in the last {m32} slices of each block): {ms / args.steps:.2f} ms/step, "
-          f"{value:.4g} updates/s, {mixed}", file=sys.stderr, flush=True)
+    print(f"[bench] mixed: {ms / args.steps:.2f} ms/step, {value:.4g} updates/s, {mixed}", file=sys.stderr,
+          flush=True)
+    # the same chains with measurement after every sweep (D and G(tau_l, k))
+    n_meas = max(2, args.steps // 2)
+    ms_meas = timed_sweeps(ctx, stream, n_meas, measure=True)
+    value_meas = updates_per_step * n_meas / (ms_meas / 1e3)
+    print(f"[bench] mixed with measurement: {ms_meas / n_meas:.2f} ms/step", file=sys.stderr, flush=True)
+    ckpt = ctx.save()
+    field0 = ctx.field(0, 0)
 
-    # sampled chains against the oracle's G computed from scratch for the GPU's field
-    max_dg = None
-    try:
-        if args.no_oracle_check:
-            raise RuntimeError("not requested")
-        import oracle
-        o = oracle.Chain(p["L"], p["U"], T_HOP, p["beta"], p["dtau"], BASE_SEED, 0, 0, n_stab)
-        errs = []
-        for c in (0, C - 1):
-            f = ctx.field(0, c)
-            for s in range(2):
-                g = ctx.green(0, c, s)
-                errs.append(float(np.max(np.abs(g - o.fresh_green(1, s, f)))))
-        max_dg = max(errs)
-    except Exception as e:  # noqa: BLE001
-        print(f"[bench] oracle comparison skipped: {e}", file=sys.stderr)
-    del ctx
+    # 2. FP32 error against the FP64 path on one identical history (two blocks)
+    m32_err = max(1, m32) if m32 > 0 else 2
+    fp32_err, fp64_slices_identical = fp32_error_on_identical_history(bss, inst, field0, k, n_stab, m32_err,
+                                                                      2 * n_stab)
+    print(f"[bench] FP32 slices ({m32_err} per block) vs FP64 path on one history: max rel|dG| {fp32_err:.3e}, "
+          f"FP64 slices identical: {fp64_slices_identical}", file=sys.stderr, flush=True)
 
-    fp64 = None
-    fp64_value = None
+    # 3. the FP64 path
+    fp64, fp64_value = None, None
     if not args.no_fp64:
-        ctx64, ms64, st64, _ = run_path(bss, inst, "fp64", k, n_stab, args.steps, args.warmup, flags=hflags)
+        ctx64, _, ms64, st64 = run_path(bss, inst, "fp64", k, n_stab, args.steps, args.warmup, flags=hflags)
         fp64_value = updates_per_step * args.steps / (ms64 / 1e3)
         fp64 = dict(summary(st64), value=fp64_value, ms_per_step=ms64 / args.steps)
-        print(f"[bench] fp64: {ms64 / args.steps:.2f} ms/step, {fp64_value:.4g} updates/s, {summary(st64)}",
-              file=sys.stderr, flush=True)
+        print(f"[bench] fp64: {ms64 / args.steps:.2f} ms/step, {fp64_value:.4g} updates/s", file=sys.stderr,
+              flush=True)
         del ctx64
-        # every slice in FP32: faster, but its drift is far outside any bound
-        ctx32, ms32, st32, _ = run_path(bss, inst, "mixed", k, n_stab, max(2, args.steps // 2), 2,
-                                        fp32_slices=n_stab, flags=hflags)
+    all32 = None
+    if args.all_fp32:
+        ctx32, _, ms32, st32 = run_path(bss, inst, "mixed", k, n_stab, max(2, args.steps // 2), 2,
+                                        fp32_slices=n_stab, flags=hflags, drift_abort=0.0)
         all32 = dict(summary(st32), value=updates_per_step * max(2, args.steps // 2) / (ms32 / 1e3),
-                     ms_per_step=ms32 / max(2, args.steps // 2))
+                     ms_per_step=ms32 / max(2, args.steps // 2), valid=False)
         print(f"[bench] all slices FP32 (not valid at this coupling): {all32}", file=sys.stderr, flush=True)
         del ctx32
-    else:
-        all32 = None
 
-    # the same sweeps with e^{-+dtau K} applied through its Kronecker factors
-    # (an option of the library; the headline applies it as dense MFMA GEMMs)
+    # 4. the Kronecker-factor option of e^{-+dtau K} on the same workload
     kron = None
     if not args.no_kronecker and not kron_head:
-        ctxk, msk, stk, _ = run_path(bss, inst, "mixed", k, n_stab, args.steps, args.warmup,
+        ctxk, _, msk, stk = run_path(bss, inst, "mixed", k, n_stab, args.steps, args.warmup,
                                      flags=bss.FLAG_KRONECKER_HOPPING)
         kval = updates_per_step * args.steps / (msk / 1e3)
         kron = dict(summary(stk), value=kval, ms_per_step=msk / args.steps, speedup_vs_headline=kval / value)
         del ctxk
-        if not args.no_fp64:
-            ctxk, msk, stk, _ = run_path(bss, inst, "fp64", k, n_stab, args.steps, args.warmup,
-                                         flags=bss.FLAG_KRONECKER_HOPPING)
-            kron["fp64_path"] = dict(summary(stk), value=updates_per_step * args.steps / (msk / 1e3),
-                                     ms_per_step=msk / args.steps)
-            del ctxk
         print(f"[bench] Kronecker hopping: {kron}", file=sys.stderr, flush=True)
 
-    # per-kernel-family HIP-event timings of the headline path, with the
-    # chains in one shard: with several shards their launches overlap, and an
-    # event pair would time other shards' work as well
+    # 5. roofline of the dominant kernel family in the timed configuration
     psteps = max(2, args.steps // 2)
-    saved = os.environ.get("BSS_SHARDS")
-    os.environ["BSS_SHARDS"] = "1"
-    try:
-        ctxp, msp, stp, prof = run_path(bss, inst, "mixed", k, n_stab, psteps, 2, profile=True, flags=hflags)
-    finally:
-        if saved is None:
-            del os.environ["BSS_SHARDS"]
-        else:
-            os.environ["BSS_SHARDS"] = saved
-    del ctxp
+    msp, stp, prof = profile_pass(bss, inst, k, n_stab, m32, ckpt, psteps, hflags)
     acc = stp["accepted"] / max(1, stp["proposals"])
-    # the chains are split into shards with launches of their own: a launch
-    # covers one shard's matrices
     shards = max(1, stp["shards"])
     Cl = C / shards
     mats = 2 * Cl
     fams = sorted(((f, v) for f, v in prof.items() if v[0] > 0), key=lambda kv: -kv[1][1])
     bound_time = 0.0
+    families = {}
     for fam, (launches, tot) in fams:
-        amount, pk, _ = family_model(fam, N, mats, Cl, acc, k, kron_head)
+        amount, pk, bound = family_model(fam, N, mats, Cl, acc, k, kron_head)
+        entry = {"launches": launches, "ms_per_step": round(tot / psteps, 3),
+                 "avg_launch_ms": round(tot / launches, 5)}
         if amount:
             bound_time += amount * launches / pk
+            entry.update(bound=bound, frac=round(amount / (tot / launches / 1e3) / pk, 4))
+        families[fam] = entry
     dom, (launches, tot) = fams[0]
-    avg_ms = tot / max(1, launches)
+    avg_ms = tot / launches
     amount, peak, bound = family_model(dom, N, mats, Cl, acc, k, kron_head)
     achieved = amount / (avg_ms / 1e3) if amount else None
     scale = 1e9 if bound == "hbm" else 1e12
@@ -298,54 +390,60 @@ def main():
                 "peak": peak / scale if peak else None, "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
                 "frac": (achieved / peak) if (achieved and peak) else None, "traffic": traffic_of(dom, args.hopping),
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                "avg_launch_ms": avg_ms, "launches": launches, "shards": shards,
-                "matrices_per_launch": mats,
-                "bound_time_fraction_of_sweep": bound_time / (msp / 1e3),
-                "breakdown_ms_per_step": {kf: round(v[1] / psteps, 3) for kf, v in fams},
-                "families": {kf: _family_roofline(kf, v, N, mats, Cl, acc, k, kron_head) for kf, v in fams}}
-    print(f"[bench] profile ({msp / psteps:.2f} ms/step): {roofline['breakdown_ms_per_step']}", file=sys.stderr,
+                "algorithmic_per_launch": amount, "avg_launch_ms": avg_ms, "launches": launches,
+                "shards": shards, "matrices_per_launch": mats, "fp32_slices": m32,
+                "profile_pass_ms_per_step": msp / psteps,
+                "bound_time_fraction_of_sweep": bound_time / (msp / 1e3), "families": families}
+    print(f"[bench] profile pass ({msp / psteps:.2f} ms/step): dominant {dom}, {families}", file=sys.stderr,
           flush=True)
 
-    # the multigrid batch: 16 uneven instances x 32 chains, graph replays
-    # against direct launches
+    # 6. the forced rank-1 path: HBM rate of the flip kernel
+    rank1 = None if args.no_rank1 else rank1_pass(bss, inst, 2)
+    if rank1:
+        print(f"[bench] rank-1 path: {rank1}", file=sys.stderr, flush=True)
+
+    # 7. the multigrid batch: 16 uneven instances x 32 chains
     batch = None
     if not args.no_batch:
         c3 = CONFIGS["C3"]
         insts = [dict(L=q["L"], U=q["U"], t=T_HOP, beta=q["beta"], dtau=q["dtau"], seed=BASE_SEED,
                       n_chains=c3["chains"]) for q in c3["instances"]]
-        v_graph, ms_graph, used_graph = run_batch(bss, insts, 5, 3, 0)
-        v_direct, ms_direct, _ = run_batch(bss, insts, 5, 3, bss.FLAG_NO_GRAPH)
+        v_graph, ms_graph, used_graph, params = run_batch(bss, insts, 5, 3, 0)
+        v_direct, ms_direct, _, _ = run_batch(bss, insts, 5, 3, bss.FLAG_NO_GRAPH)
         batch = {"workload": "16 instances L in {6,8,10,12} x dtau in {0.4,0.5,0.625,0.8}, U=2, beta=20, "
-                             "32 chains each, FP64, automatic k and n_stab",
-                 "value": v_graph, "unit": "updates/s", "ms_per_step": ms_graph, "sweep_graph": used_graph,
-                 "direct_launch_value": v_direct, "direct_launch_ms_per_step": ms_direct}
-        print(f"[bench] batch C3: {batch}", file=sys.stderr, flush=True)
+                             "32 chains each, FP64", "value": v_graph, "unit": "updates/s",
+                 "ms_per_step": ms_graph, "sweep_graph": used_graph, "direct_launch_value": v_direct,
+                 "direct_launch_ms_per_step": ms_direct, "instances": params}
+        print(f"[bench] batch: {batch}", file=sys.stderr, flush=True)
 
-    cpu = None
+    # 8. the cpu_baseline leg: the oracle on the host, and the sampled check
+    cpu, d_exact, d_same = None, None, None
     if not args.no_cpu_baseline:
-        import oracle
-        cores = min(len(os.sched_getaffinity(0)), 16)
-        nch = args.cpu_chains or cores
-        sec, used = oracle.run_chains(p["L"], p["U"], T_HOP, p["beta"], p["dtau"], BASE_SEED, nch, n_stab, 1, cores)
-        cpu = {"value": nch * N * lam / sec, "unit": "updates/s", "cores": used, "kind": "oracle",
-               "sample": f"{nch} chains x 1 sweep of the same 16x16 workload from the generator-drawn field "
-                         f"(FP64 oracle: rank-1 updates, recomputation from scratch), {sec:.1f} s"}
-        print(f"[bench] cpu oracle: {cpu}", file=sys.stderr, flush=True)
+        cpu, d_exact, d_same = cpu_baseline_leg(p, n_stab, ctx, C)
+        print(f"[bench] cpu oracle: {cpu}; sampled sweep-end max rel|dG|: vs exact {d_exact:.3e}, vs oracle at "
+              f"n_stab={n_stab} {d_same:.3e}", file=sys.stderr, flush=True)
+    del ctx
 
     out = {
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic (Markov chains from seeded Philox fields)",
         "config": {"workload": f"16x16 Hubbard BSS-QMC sweep, t=0.25, U=2, beta=20, dtau=0.5 (Lambda=40), "
-                               f"{C} chains, k={k}, n_stab={n_stab}, FP32 in the last {m32} slices of each block, "
+                               f"{C} chains, k={k}, n_stab={n_stab}, FP32 in the last slices of each block as the "
+                               f"drift controller allows (target 1e-3), "
                                + ("e^{-+dtau K} through its Kronecker factors" if kron_head
                                   else "wraps and block products as dense MFMA GEMMs"),
                    "L": p["L"], "chains": C, "beta": p["beta"], "dtau": p["dtau"], "U": p["U"], "k": k,
-                   "n_stab": n_stab, "fp32_slices": m32, "hopping": args.hopping, "shards": st["shards"]},
+                   "n_stab": n_stab, "fp32_slices_final": m32, "hopping": args.hopping, "shards": st["shards"]},
         "drift_rel_max": mixed["drift_rel_max"], "drift_rel_mean": mixed["drift_rel_mean"],
-        "max_dG_vs_oracle_sweep_end": max_dg, "acceptance": mixed["acceptance"],
+        "fp32_drift_bound": 1e-3, "fp32_fraction": mixed["fp32_fraction"], "acceptance": mixed["acceptance"],
+        "fp32_rejected_ratios": mixed["fp32_rejected"], "fp32_fused": mixed["fp32_fused"],
+        "fp32_max_dG_vs_fp64_path": fp32_err, "fp32_slices_for_that_check": m32_err,
+        "fp64_slices_bit_identical": fp64_slices_identical,
+        "max_dG_vs_oracle_sweep_end": d_exact, "max_dG_vs_oracle_same_n_stab": d_same,
+        "value_with_measurement": value_meas, "ms_per_step_with_measurement": ms_meas / n_meas,
         "fp64_path": fp64, "speedup_vs_fp64": (value / fp64_value) if fp64_value else None,
-        "all_fp32_bulk": all32, "kronecker_hopping": kron, "multigrid_batch": batch,
+        "all_fp32_bulk": all32, "kronecker_hopping": kron, "rank1_path": rank1, "multigrid_batch": batch,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out))

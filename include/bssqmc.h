@@ -124,8 +124,15 @@ typedef struct {
                             about e^{2 lambda}), never above the largest s with
                             2^-24 e^{2 lambda s} <= 1e-5 (may be 0 at strong
                             coupling).  bss_sweep then waits for each sweep's
-                            recomputations before issuing the next.  Ignored in
-                            FP64 mode.                                             */
+                            recomputations before issuing the next, and launches
+                            its kernels directly (no captured sweep).  In these
+                            FP32 slices a finite ratio R <= 0 (FP32 rounding of
+                            a G whose entries reach 1e2..1e3) is rejected and
+                            counted (bss_stats.fp32_rejected) instead of being a
+                            numerical failure, and the instance runs in FP64
+                            from the next sweep on (bss_stats.fp32_fused).
+                            With a fixed count, or when replaying a history,
+                            such a ratio stays a failure.  Ignored in FP64 mode. */
   double fp32_drift_target; /* the controller's bound on the relative drift;
                             0 = 1e-3                                              */
 } bss_options;
@@ -158,6 +165,8 @@ typedef struct {
                             own streams (every kernel launch covers one group)  */
   double fp32_fraction;  /* fraction of the slices swept since creation or the
                             last bss_reset_stats that ran in FP32               */
+  int64_t fp32_rejected; /* ratios <= 0 rejected in the controller's FP32 slices */
+  int32_t fp32_fused;    /* 1 once such a ratio switched the instance to FP64   */
 } bss_stats;
 
 /* Per-kernel launch timing collected under BSS_FLAG_PROFILE. */

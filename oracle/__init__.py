@@ -82,7 +82,7 @@ def lib():
         L.orc_gtau0.argtypes = [vp, vp, i32, i32, vp]
         L.orc_measure.argtypes = [vp, P(dbl), vp]
         L.orc_get_stats.argtypes = [vp, P(OrcStats)]
-        L.orc_run_chains.argtypes = [i32, dbl, dbl, dbl, dbl, u64, i32, i32, i32, i32, P(i32)]
+        L.orc_run_chains.argtypes = [i32, dbl, dbl, dbl, dbl, u64, i32, i32, i32, i32, i32, P(i32)]
         L.orc_run_chains.restype = dbl
         _lib = L
     return _lib
@@ -258,11 +258,11 @@ class Chain:
         return d.value, gtk
 
 
-def run_chains(L, U, t, beta, dtau, seed, n_chains, n_stab, n_sweeps, n_threads=0):
-    """Time n_sweeps sweeps of n_chains chains (OpenMP over chains).
-    Returns (seconds, threads used)."""
+def run_chains(L, U, t, beta, dtau, seed, n_chains, n_stab, n_sweeps, n_threads=0, n_warm=0):
+    """Time n_sweeps sweeps of n_chains chains (OpenMP over chains) after
+    n_warm untimed sweeps.  Returns (seconds, threads used)."""
     used = ctypes.c_int()
-    sec = lib().orc_run_chains(L, U, t, beta, dtau, seed, n_chains, n_stab, n_sweeps,
+    sec = lib().orc_run_chains(L, U, t, beta, dtau, seed, n_chains, n_stab, n_warm, n_sweeps,
                                n_threads, ctypes.byref(used))
     if sec < 0:
         raise ValueError("oracle rejected the parameters")

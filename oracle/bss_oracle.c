@@ -670,7 +670,7 @@ void orc_measure(const orc_chain *c, double *docc, double *gtk) {
 
 /* ------------------------------------------------------------------------ */
 double orc_run_chains(int L, double U, double t, double beta, double dtau,
-                      uint64_t seed, int n_chains, int n_stab, int n_sweeps,
+                      uint64_t seed, int n_chains, int n_stab, int n_warm, int n_sweeps,
                       int n_threads, int *threads_used) {
   orc_chain **ch = (orc_chain **)calloc((size_t)n_chains, sizeof(orc_chain *));
 #ifdef _OPENMP
@@ -680,6 +680,12 @@ double orc_run_chains(int L, double U, double t, double beta, double dtau,
   for (int c = 0; c < n_chains; ++c) ch[c] = orc_create(L, U, t, beta, dtau, seed, 0, c, n_stab);
   for (int c = 0; c < n_chains; ++c)
     if (!ch[c]) { for (int d = 0; d < n_chains; ++d) orc_destroy(ch[d]); free(ch); return -1.0; }
+  if (n_warm > 0) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static)
+#endif
+    for (int c = 0; c < n_chains; ++c) orc_step_slices(ch[c], n_warm * ch[c]->Lam, NULL, NULL);
+  }
   int used = 1;
   double t0 = 0.0, t1 = 0.0;
 #ifdef _OPENMP

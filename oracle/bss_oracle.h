@@ -111,11 +111,12 @@ typedef struct {
 } orc_stats;
 void orc_get_stats(const orc_chain *c, orc_stats *out);
 
-/* CPU baseline: run n_chains chains of one instance for n_sweeps sweeps with
- * OpenMP over chains (one chain per thread).  Returns seconds spent sweeping
- * (creation excluded); *threads_used receives the thread count. */
+/* CPU baseline: run n_chains chains of one instance for n_warm untimed and
+ * then n_sweeps timed sweeps with OpenMP over chains (one chain per thread).
+ * Returns the seconds of the timed sweeps; *threads_used receives the thread
+ * count. */
 double orc_run_chains(int L, double U, double t, double beta, double dtau,
-                      uint64_t seed, int n_chains, int n_stab, int n_sweeps,
+                      uint64_t seed, int n_chains, int n_stab, int n_warm, int n_sweeps,
                       int n_threads, int *threads_used);
 
 #ifdef __cplusplus

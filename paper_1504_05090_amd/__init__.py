@@ -51,7 +51,8 @@ class Stats(ctypes.Structure):
                 ("Lambda", ctypes.c_int32), ("delay_k", ctypes.c_int32), ("n_stab", ctypes.c_int32),
                 ("fp32_slices", ctypes.c_int32), ("drift_rel_max", ctypes.c_double),
                 ("drift_rel_mean", ctypes.c_double), ("sweep_graph", ctypes.c_int32), ("shards", ctypes.c_int32),
-                ("fp32_fraction", ctypes.c_double)]
+                ("fp32_fraction", ctypes.c_double), ("fp32_rejected", ctypes.c_int64),
+                ("fp32_fused", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):

@@ -18,6 +18,14 @@
 //   x = (Delta/R)(e_i - c),    y = r,
 // and every d_j drops by x_j y_j.  When k pairs are stored (and at the end of
 // the slice) they are flushed into G0 by a rank-k MFMA product.
+//
+// Precision: the arithmetic (T) is FP64.  G is stored (S) in FP64, or in FP32
+// for the FP32 slices of mixed precision: then G is converted on load and
+// rounded to FP32 when the flush stores it, so the stored values carry one
+// FP32 rounding relative to themselves.  With FP32 arithmetic the rank-k
+// product would sum terms |x_m| |y_m| up to |Delta/R| max|G|^2 (~1e6 at
+// 16 x 16, beta = 20, where max|G| reaches ~100) into entries of order 1,
+// and its absolute rounding error of ~1e-1 turns determinant ratios negative.
 #include <utility>
 
 #include "common.h"
@@ -31,8 +39,8 @@ namespace {
 // the accumulator input (D = (-X) Y^T + G0).  Rows of -X are staged in LDS
 // by their owners in blocks of fb rows, Y^T once; each wavefront loads a
 // batch of G0 tiles before its MFMAs so that the global latencies overlap.
-template <typename T, int KM>
-__device__ void flush_spin(T *G, int N, int fb, const T (&xs)[KM], const T (&ys)[KM], T *Xs, T *Ys) {
+template <typename T, typename S, int KM>
+__device__ void flush_spin(S *G, int N, int fb, const T (&xs)[KM], const T (&ys)[KM], T *Xs, T *Ys) {
   constexpr int TB = 8;   // tiles in flight per wavefront
   const int j = threadIdx.x, lane = j & 63, w = j >> 6, nw = blockDim.x >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
@@ -60,7 +68,7 @@ __device__ void flush_spin(T *G, int N, int fb, const T (&xs)[KM], const T (&ys)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = i0 + tr * 16 + Mfma<T>::row(lane, r), col = tc * 16 + l16;
-          acc[b][r] = (tile < ntiles && row < i0 + nrb && col < N) ? G[(long)row * N + col] : (T)0;
+          acc[b][r] = (tile < ntiles && row < i0 + nrb && col < N) ? (T)G[(long)row * N + col] : (T)0;
         }
       }
 #pragma unroll
@@ -81,7 +89,7 @@ __device__ void flush_spin(T *G, int N, int fb, const T (&xs)[KM], const T (&ys)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = i0 + tr * 16 + Mfma<T>::row(lane, r), col = tc * 16 + l16;
-            if (row < i0 + nrb && col < N) G[(long)row * N + col] = acc[b][r];
+            if (row < i0 + nrb && col < N) G[(long)row * N + col] = (S)acc[b][r];
           }
         }
       }
@@ -90,7 +98,7 @@ __device__ void flush_spin(T *G, int N, int fb, const T (&xs)[KM], const T (&ys)
   __syncthreads();
 }
 
-template <typename T, int KM, int MAXT>
+template <typename T, typename S, int KM, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
   extern __shared__ char smem_raw[];
   T *Xs = (T *)smem_raw;                                  // [fb][KM+1]
@@ -108,7 +116,7 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
   const int c = blockIdx.x;
   const bool own = j < N;
   const long NN = (long)N * N;
-  T *G[2] = {(T *)a.G + (2L * c) * NN, (T *)a.G + (2L * c + 1) * NN};
+  S *G[2] = {(S *)a.G + (2L * c) * NN, (S *)a.G + (2L * c + 1) * NN};
   int8_t *hl = a.h + ((long)c * a.Lam + (a.l - 1)) * N;
   const int64_t sweep = *a.sweep;
 
@@ -140,7 +148,8 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
   __syncthreads();
 
   int m = 0, pos = 0, par = 0;
-  bool badj = false;
+  int badj = 0;   // 1: ratio <= 0, 2: ratio not finite
+  int softj = 0;  // 1: ratio <= 0 in a guarded FP32 slice (rejected, counted)
   for (;;) {
     bool acc = false;
     if (own && j >= pos) {
@@ -151,7 +160,8 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
       // the last evaluation is the site's proposal: every weight of eq. (3)
       // is positive at half filling, so a ratio that is not a finite positive
       // number is an error whether or not it is accepted
-      badj = !(R > 0.0) || !isfinite(R);
+      softj = (a.fp32_guard && isfinite(R) && !(R > 0.0)) ? 1 : 0;
+      badj = softj ? 0 : (!isfinite(R) ? 2 : (R > 0.0 ? 0 : 1));
     }
     const unsigned long long bal = __ballot(acc);
     if (lane == 0) first[par][w] = bal ? (w * 64 + __ffsll((long long)bal) - 1) : 0x7fffffff;
@@ -210,8 +220,8 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
     // and the one after can only write these once every thread has passed
     // the next ballot barrier, i.e. finished reading them.
     if (m == a.k) {
-      flush_spin<T, KM>(G[0], N, a.fb, xs[0], ys[0], Xs, Ys);
-      flush_spin<T, KM>(G[1], N, a.fb, xs[1], ys[1], Xs, Ys);
+      flush_spin<T, S, KM>(G[0], N, a.fb, xs[0], ys[0], Xs, Ys);
+      flush_spin<T, S, KM>(G[1], N, a.fb, xs[1], ys[1], Xs, Ys);
 #pragma unroll
       for (int s = 0; s < KM; ++s) { xs[0][s] = xs[1][s] = ys[0][s] = ys[1][s] = (T)0; }
       d[0] = own ? (double)G[0][(long)j * N + j] : 0.0;
@@ -220,15 +230,15 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
     }
   }
   if (m > 0) {
-    flush_spin<T, KM>(G[0], N, a.fb, xs[0], ys[0], Xs, Ys);
-    flush_spin<T, KM>(G[1], N, a.fb, xs[1], ys[1], Xs, Ys);
+    flush_spin<T, S, KM>(G[0], N, a.fb, xs[0], ys[0], Xs, Ys);
+    flush_spin<T, S, KM>(G[1], N, a.fb, xs[1], ys[1], Xs, Ys);
   }
   // diagonal factors of the updated slice for the wrap: D = e^{sigma lambda h}
   if (own) {
-    T *dv0 = (T *)a.dv + (2L * c) * 2 * N;
-    T *dv1 = dv0 + 2 * N;
-    const T up = hj > 0 ? (T)a.elam : (T)a.emlam;
-    const T dn = hj > 0 ? (T)a.emlam : (T)a.elam;
+    S *dv0 = (S *)a.dv + (2L * c) * 2 * N;
+    S *dv1 = dv0 + 2 * N;
+    const S up = hj > 0 ? (S)a.elam : (S)a.emlam;
+    const S dn = hj > 0 ? (S)a.emlam : (S)a.elam;
     dv0[j] = up; dv0[N + j] = dn;      // spin up: D, D^{-1}
     dv1[j] = dn; dv1[N + j] = up;      // spin down
     if (a.trace_mode == 1 && trace_idx >= 0) a.trace[trace_idx] = mine ? 1 : 0;
@@ -237,23 +247,26 @@ __global__ __launch_bounds__(MAXT) void k_flip(FlipArgs a) {
   // log-weight of the slice's accepted ratios (FP64), and the check that
   // every proposed ratio was positive and finite
   const int nacc = s_acc;
-  double lg = 0.0, bad = badj ? 1.0 : 0.0, neg = 0.0;
+  double lg = 0.0, bad = (double)badj, neg = 0.0, soft = (double)softj;
   for (int q = j; q < nacc; q += blockDim.x) {
     const double R = s_R[q];
-    if (!(R > 0.0) || !isfinite(R)) bad = 1.0;
+    if (!isfinite(R)) bad = 2.0;
+    else if (!(R > 0.0)) bad = fmax(bad, 1.0);
     if (R < 0.0) neg += 1.0;
     lg += log(fabs(R));
   }
   lg = block_sum(lg, red);
   bad = block_max(bad, red);
   neg = block_sum(neg, red);
+  soft = block_sum(soft, red);
   if (j == 0) {
     ChainStats *st = a.stats + c;
     st->proposals += N;
     st->accepted += nacc;
     st->logw += lg;
     st->negs += (int)neg;
-    if (bad > 0.0) atomicOr(a.err, 1);
+    st->fp32_rejected += (int)soft;
+    if (bad > 0.0) atomicOr(a.err, bad > 1.5 ? (1 | 16) : (1 | 32));
   }
 }
 
@@ -315,17 +328,6 @@ __device__ __forceinline__ void row_fmac4(double &c0, double &c1, double &r0, do
       : "+v"(c0), "+v"(c1), "+v"(r0), "+v"(r1)
       : "v"(vy0), "v"(vy1), "v"(vx0), "v"(vx1), "v"(x0), "v"(x1), "v"(y0), "v"(y1), "n"(Q));
 }
-template <int Q>
-__device__ __forceinline__ void row_fmac4(float &c0, float &c1, float &r0, float &r1, float vy0, float vy1, float vx0,
-                                          float vx1, float x0, float x1, float y0, float y1) {
-  asm("s_nop 1\n\t"
-      "v_fmac_f32_dpp %0, %4, %8 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %1, %5, %9 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %2, %6, %10 row_newbcast:%c12 row_mask:0xf bank_mask:0xf\n\t"
-      "v_fmac_f32_dpp %3, %7, %11 row_newbcast:%c12 row_mask:0xf bank_mask:0xf"
-      : "+v"(c0), "+v"(c1), "+v"(r0), "+v"(r1)
-      : "v"(vy0), "v"(vy1), "v"(vx0), "v"(vx1), "v"(x0), "v"(x1), "v"(y0), "v"(y1), "n"(Q));
-}
 // c_s = sum_q xs_s[q] vy_s[q], r_s = sum_q vx_s[q] ys_s[q] (s = both spins),
 // accumulated in q order, with vy_s[q], vx_s[q] held by lane q of the row
 template <typename T, int H, int... Q>
@@ -336,8 +338,8 @@ __device__ __forceinline__ void row_dots(T (&c)[2], T (&r)[2], const T (&vy)[2],
 
 // G0 <- G0 - X Y^T for one spin with the pairs split over the two lanes of
 // each site (same MFMA scheme as flush_spin).
-template <typename T, int KM>
-__device__ void flush_pairs(T *G, int N, int fb, int ldy, const T (&xs)[KM / 2], const T (&ys)[KM / 2], T *Xs,
+template <typename T, typename S, int KM>
+__device__ void flush_pairs(S *G, int N, int fb, int ldy, const T (&xs)[KM / 2], const T (&ys)[KM / 2], T *Xs,
                             T *Ys) {
   // tiles per wavefront: two batches of TP tiles alternate, the next batch's
   // G tiles loading while the current batch runs its MFMAs (with FP64 MFMA
@@ -375,7 +377,7 @@ __device__ void flush_pairs(T *G, int N, int fb, int ldy, const T (&xs)[KM / 2],
         for (int r = 0; r < 4; ++r) {
           const int row = i0 + tr * 16 + Mfma<T>::row(lane, r), col = tc * 16 + l16;
           const bool in = tile < ntiles && row < i0 + nrb && col < N;
-          const T v = G[(unsigned)(min(row, N - 1) * N + min(col, N - 1))];
+          const T v = (T)G[(unsigned)(min(row, N - 1) * N + min(col, N - 1))];
           acc[b][r] = in ? v : (T)0;
         }
       }
@@ -409,7 +411,7 @@ __device__ void flush_pairs(T *G, int N, int fb, int ldy, const T (&xs)[KM / 2],
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = i0 + tr[b] * 16 + Mfma<T>::row(lane, r), col = tc[b] * 16 + l16;
-            if (row < i0 + nrb && col < N) G[(unsigned)(row * N + col)] = acc[b][r];
+            if (row < i0 + nrb && col < N) G[(unsigned)(row * N + col)] = (S)acc[b][r];
           }
         }
       }
@@ -427,7 +429,7 @@ __device__ void flush_pairs(T *G, int N, int fb, int ldy, const T (&xs)[KM / 2],
   __syncthreads();
 }
 
-template <typename T, int KM>
+template <typename T, typename S, int KM>
 __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
   static_assert(KM % 8 == 0, "pairs are split over two lanes and staged in steps of 4");
   constexpr int H = KM / 2;
@@ -447,7 +449,7 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
   const int c = blockIdx.x;
   const bool own = j < N;
   const long NN = (long)N * N;
-  T *G[2] = {(T *)a.G + (2L * c) * NN, (T *)a.G + (2L * c + 1) * NN};
+  S *G[2] = {(S *)a.G + (2L * c) * NN, (S *)a.G + (2L * c + 1) * NN};
   int8_t *hl = a.h + ((long)c * a.Lam + (a.l - 1)) * N;
   const int64_t sweep = *a.sweep;
 
@@ -478,7 +480,8 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
   __syncthreads();
 
   int m = 0, pos = 0, par = 0, nacc = 0;   // nacc: acceptances so far, the same in every lane
-  bool badj = false;
+  int badj = 0;   // 1: ratio <= 0, 2: ratio not finite
+  int softj = 0;  // 1: ratio <= 0 in a guarded FP32 slice (rejected, counted)
   for (;;) {
     bool acc = false;
     if (own && j >= pos) {
@@ -489,7 +492,8 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
       // the last evaluation is the site's proposal: every weight of eq. (3)
       // is positive at half filling, so a ratio that is not a finite positive
       // number is an error whether or not it is accepted
-      badj = !(R > 0.0) || !isfinite(R);
+      softj = (a.fp32_guard && isfinite(R) && !(R > 0.0)) ? 1 : 0;
+      badj = softj ? 0 : (!isfinite(R) ? 2 : (R > 0.0 ? 0 : 1));
     }
     // both lanes of a site decide alike: look at the lanes of half 0
     const unsigned long long bal = __ballot(acc) & PL::half0;
@@ -564,8 +568,8 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
     par ^= 1;
     // no barrier: the next acceptance uses the other parity's buffers (see k_flip)
     if (m == a.k) {
-      flush_pairs<T, KM>(G[0], N, a.fb, ldy, xs[0], ys[0], Xs, Ys);
-      flush_pairs<T, KM>(G[1], N, a.fb, ldy, xs[1], ys[1], Xs, Ys);
+      flush_pairs<T, S, KM>(G[0], N, a.fb, ldy, xs[0], ys[0], Xs, Ys);
+      flush_pairs<T, S, KM>(G[1], N, a.fb, ldy, xs[1], ys[1], Xs, Ys);
 #pragma unroll
       for (int q = 0; q < H; ++q) { xs[0][q] = xs[1][q] = ys[0][q] = ys[1][q] = (T)0; }
       d[0] = own ? (double)G[0][(long)j * N + j] : 0.0;
@@ -574,40 +578,43 @@ __global__ __launch_bounds__(512) void k_flip_pairs(FlipArgs a) {
     }
   }
   if (m > 0) {
-    flush_pairs<T, KM>(G[0], N, a.fb, ldy, xs[0], ys[0], Xs, Ys);
-    flush_pairs<T, KM>(G[1], N, a.fb, ldy, xs[1], ys[1], Xs, Ys);
+    flush_pairs<T, S, KM>(G[0], N, a.fb, ldy, xs[0], ys[0], Xs, Ys);
+    flush_pairs<T, S, KM>(G[1], N, a.fb, ldy, xs[1], ys[1], Xs, Ys);
   }
   if (own && hf == 0) {
-    T *dv0 = (T *)a.dv + (2L * c) * 2 * N;
-    T *dv1 = dv0 + 2 * N;
-    const T up = hj > 0 ? (T)a.elam : (T)a.emlam;
-    const T dn = hj > 0 ? (T)a.emlam : (T)a.elam;
+    S *dv0 = (S *)a.dv + (2L * c) * 2 * N;
+    S *dv1 = dv0 + 2 * N;
+    const S up = hj > 0 ? (S)a.elam : (S)a.emlam;
+    const S dn = hj > 0 ? (S)a.emlam : (S)a.elam;
     dv0[j] = up; dv0[N + j] = dn;
     dv1[j] = dn; dv1[N + j] = up;
     if (a.trace_mode == 1 && trace_idx >= 0) a.trace[trace_idx] = mine ? 1 : 0;
   }
   __syncthreads();
-  double lg = 0.0, bad = badj ? 1.0 : 0.0, neg = 0.0;
+  double lg = 0.0, bad = (double)badj, neg = 0.0, soft = hf == 0 ? (double)softj : 0.0;   // one count per site
   for (int q = t; q < nacc; q += blockDim.x) {
     const double R = s_R[q];
-    if (!(R > 0.0) || !isfinite(R)) bad = 1.0;
+    if (!isfinite(R)) bad = 2.0;
+    else if (!(R > 0.0)) bad = fmax(bad, 1.0);
     if (R < 0.0) neg += 1.0;
     lg += log(fabs(R));
   }
   lg = block_sum(lg, red);
   bad = block_max(bad, red);
   neg = block_sum(neg, red);
+  soft = block_sum(soft, red);
   if (t == 0) {
     ChainStats *st = a.stats + c;
     st->proposals += N;
     st->accepted += nacc;
     st->logw += lg;
     st->negs += (int)neg;
-    if (bad > 0.0) atomicOr(a.err, 1);
+    st->fp32_rejected += (int)soft;
+    if (bad > 0.0) atomicOr(a.err, bad > 1.5 ? (1 | 16) : (1 | 32));
   }
 }
 
-template <typename T, int KM>
+template <typename T, typename S, int KM>
 hipError_t launch_pairs(const FlipArgs &a0, hipStream_t s) {
   FlipArgs a = a0;
   const int sites = ((a.N + 31) / 32) * 32;           // 32 sites per wavefront
@@ -620,11 +627,11 @@ hipError_t launch_pairs(const FlipArgs &a0, hipStream_t s) {
   a.fb = fb;
   const size_t lds = sizeof(T) * (size_t)fb * XLD + ybytes;
   if (threads > 512) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_flip_pairs<T, KM>), dim3(a.chains), dim3(threads), lds, s, a);
+  hipLaunchKernelGGL((k_flip_pairs<T, S, KM>), dim3(a.chains), dim3(threads), lds, s, a);
   return hipGetLastError();
 }
 
-template <typename T, int KM>
+template <typename T, typename S, int KM>
 hipError_t launch_k(const FlipArgs &a0, hipStream_t s) {
   FlipArgs a = a0;
   const int threads = ((a.N + 63) / 64) * 64;
@@ -636,32 +643,33 @@ hipError_t launch_k(const FlipArgs &a0, hipStream_t s) {
   a.fb = fb;
   const size_t lds = sizeof(T) * (size_t)fb * (KM + 1) + ybytes;
   if (threads <= 256)
-    hipLaunchKernelGGL((k_flip<T, KM, 256>), dim3(a.chains), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_flip<T, S, KM, 256>), dim3(a.chains), dim3(threads), lds, s, a);
   else if (threads <= 512)
-    hipLaunchKernelGGL((k_flip<T, KM, 512>), dim3(a.chains), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_flip<T, S, KM, 512>), dim3(a.chains), dim3(threads), lds, s, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, typename S>
 hipError_t launch_t(const FlipArgs &a, hipStream_t s) {
-  if (a.k <= 1) return launch_k<T, 1>(a, s);
+  if (a.k <= 1) return launch_k<T, S, 1>(a, s);
   if (a.N <= 256) {   // two lanes per site
-    if (a.k <= 8) return launch_pairs<T, 8>(a, s);
-    if (a.k <= 16) return launch_pairs<T, 16>(a, s);
-    if (a.k <= 32) return launch_pairs<T, 32>(a, s);
+    if (a.k <= 8) return launch_pairs<T, S, 8>(a, s);
+    if (a.k <= 16) return launch_pairs<T, S, 16>(a, s);
+    if (a.k <= 32) return launch_pairs<T, S, 32>(a, s);
     return hipErrorInvalidValue;
   }
-  if (a.k <= 8) return launch_k<T, 8>(a, s);
-  if (a.k <= 16) return launch_k<T, 16>(a, s);
-  if (a.k <= 32) return launch_k<T, 32>(a, s);
+  if (a.k <= 8) return launch_k<T, S, 8>(a, s);
+  if (a.k <= 16) return launch_k<T, S, 16>(a, s);
+  if (a.k <= 32) return launch_k<T, S, 32>(a, s);
   return hipErrorInvalidValue;
 }
 }  // namespace
 
 hipError_t flip_slice(const FlipArgs &a, bool fp64, hipStream_t s) {
-  return fp64 ? launch_t<double>(a, s) : launch_t<float>(a, s);
+  // FP64 arithmetic in both cases; G stored in FP64 or FP32
+  return fp64 ? launch_t<double, double>(a, s) : launch_t<double, float>(a, s);
 }
 
 }  // namespace bss

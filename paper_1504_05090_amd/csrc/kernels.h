@@ -29,7 +29,8 @@ struct ChainStats {
   double rdrift_max, rdrift_sum;         // the same over max(1, max_ij |G_fresh|)
   double rdrift_sweep;                   // largest relative drift of the current sweep
   int64_t drift_count;
-  int32_t negs, pad;                     // accepted ratios that were negative
+  int32_t negs;                          // accepted ratios that were negative
+  int32_t fp32_rejected;                 // finite ratios <= 0 met in guarded FP32 slices
 };
 
 // Flip phase of one slice for every chain of one instance.
@@ -46,6 +47,8 @@ struct FlipArgs {
   uint64_t seed, inst;
   const int64_t *sweep;        // device sweep counter
   int trace_mode;              // 0 none, 1 record, 2 replay
+  int fp32_guard;              // FP32-stored G: a finite ratio <= 0 is rejected and
+                               // counted (stats fp32_rejected), not an error
   uint8_t *trace;              // [sweeps][chains_total][Lam][N]
   const int64_t *trace_base;   // sweep index of trace entry 0
   int64_t trace_sweeps;        // capacity in sweeps

@@ -57,6 +57,8 @@ struct Shard {
   int m32 = 0;                           // FP32 slices at the end of each block (mixed mode)
   int m32_max = 0;                       // automatic count, the controller's ceiling
   bool adapt = false;                    // mixed mode, automatic count: adjusted after every sweep
+  bool fused = false;                    // an FP32 ratio <= 0 was met: FP64 from then on
+  int64_t fp32_rej_seen = 0;             // rejected FP32 ratios already acted on
   int64_t slices_run = 0, fp32_run = 0;  // slices swept since the last statistics reset, in FP32
   int inst = 0, chain0 = 0, Ctot = 0;
   double U = 0, t = 0, beta = 0, dtau = 0, lambda = 0;
@@ -138,9 +140,15 @@ struct bss_ctx {
   std::vector<hipEvent_t> pool;
   // captured (unmeasured) sweeps, two graphs each, keyed by the FP32 slice
   // counts of the shards they were captured with; replayed by bss_sweep
+  // Each captured sweep has event objects of its own (the fork event and each
+  // shard's main / rebuild events), used only inside its capture and destroyed
+  // after its executable graphs: no event object is shared between a capture
+  // and direct launches or another capture.
   struct SweepGraph {
     std::vector<int> key;
     hipGraphExec_t g[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev;   // [2 * shard]: main, rebuild
   };
   std::vector<SweepGraph> gcache;
   bool graphs = false;   // capture and replay sweeps (off: NO_GRAPH, PROFILE, or capture failed)
@@ -547,6 +555,10 @@ struct Exec {
     a.seed = I.seed; a.inst = (uint64_t)I.inst;
     a.sweep = I.sweep_ctr;
     a.trace_mode = (c->opt.flags & BSS_FLAG_RECORD_TRACE) ? 1 : ((c->opt.flags & BSS_FLAG_REPLAY_TRACE) ? 2 : 0);
+    // FP32 slices of the drift controller: a finite ratio <= 0 (FP32 rounding
+    // of a G with large entries) is rejected and counted; the controller then
+    // runs the instance in FP64
+    a.fp32_guard = (!I.cur64 && I.adapt && a.trace_mode != 2) ? 1 : 0;
     a.trace = U.trace; a.trace_base = U.trace_base; a.trace_sweeps = U.trace_cap;
     a.stats = I.stats; a.err = c->err;
     Timed tm(c, I.cur64 ? F_FLIP64 : F_FLIP32, s);
@@ -695,7 +707,8 @@ bss_status check_err(bss_ctx *c) {
   if (herr) {
     c->poisoned = true;
     std::string m = "numerical failure:";
-    if (herr & 1) m += " non-positive or non-finite accepted ratio;";
+    if (herr & 16) m += " non-finite determinant ratio;";
+    if (herr & 32) m += " non-positive determinant ratio;";
     if (herr & 2) m += " wrap drift above drift_abort;";
     if (herr & 4) m += " non-finite recomputed Green function;";
     return fail(c, BSS_E_NUMERICAL, m);
@@ -914,12 +927,32 @@ bool capture_range(bss_ctx *c, int l_from, int l_to, hipGraphExec_t *out) {
 // so that form is not captured.  Measured sweeps always launch directly.
 // Returns false if the runtime refuses a capture; the caller then stays with
 // direct launches.
-bool capture_sweep(bss_ctx *c, hipGraphExec_t out[2]) {
+void release_graph(bss_ctx::SweepGraph &sg) {
+  for (auto &g : sg.g)
+    if (g) { hipGraphExecDestroy(g); g = nullptr; }
+  if (sg.ev_fork) { hipEventDestroy(sg.ev_fork); sg.ev_fork = nullptr; }
+  for (auto &e : sg.ev)
+    if (e) { hipEventDestroy(e); e = nullptr; }
+}
+
+bool capture_sweep(bss_ctx *c, bss_ctx::SweepGraph &sg) {
   const size_t n = c->sh.size();
+  // the capture's own events
+  bool ok = hipEventCreateWithFlags(&sg.ev_fork, hipEventDisableTiming) == hipSuccess;
+  sg.ev.assign(2 * n, nullptr);
+  for (auto &e : sg.ev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+  if (!ok) { release_graph(sg); return false; }
+  hipEvent_t keep_fork = c->ev_fork;
+  std::vector<hipEvent_t> keep(2 * n);
   std::vector<bool> pend(n), cur(n), stale(n);
   int l_first = 1 << 30, lam_max = 0;
+  c->ev_fork = sg.ev_fork;
   for (size_t i = 0; i < n; ++i) {
     Shard &I = c->sh[i];
+    keep[2 * i] = I.ev_main;
+    keep[2 * i + 1] = I.ev_left;
+    I.ev_main = sg.ev[2 * i];
+    I.ev_left = sg.ev[2 * i + 1];
     pend[i] = I.left_pending;
     cur[i] = I.cur64;
     stale[i] = I.left_stale;
@@ -928,27 +961,25 @@ bool capture_sweep(bss_ctx *c, hipGraphExec_t out[2]) {
     l_first = std::min(l_first, std::min(I.n_stab, I.Lam));
     lam_max = std::max(lam_max, I.Lam);
   }
-  hipGraphExec_t ga = nullptr, gb = nullptr;
-  bool ok = capture_range(c, 1, l_first - 1, &ga);
+  ok = capture_range(c, 1, l_first - 1, &sg.g[0]);
   // the first part's join has ordered the context stream after the rebuilds
   for (auto &I : c->sh) I.left_pending = false;
-  if (ok) ok = capture_range(c, l_first, lam_max, &gb);
-  // a capture enqueues nothing: restore the host-side state it advanced
+  if (ok) ok = capture_range(c, l_first, lam_max, &sg.g[1]);
+  // a capture enqueues nothing: restore the host-side state it advanced and
+  // the events of direct launches
+  c->ev_fork = keep_fork;
   for (size_t i = 0; i < n; ++i) {
-    c->sh[i].left_pending = pend[i];
-    c->sh[i].cur64 = cur[i];
-    c->sh[i].left_stale = stale[i];
+    Shard &I = c->sh[i];
+    I.ev_main = keep[2 * i];
+    I.ev_left = keep[2 * i + 1];
+    I.left_pending = pend[i];
+    I.cur64 = cur[i];
+    I.left_stale = stale[i];
   }
   c->poisoned = false;
   (void)hipGetLastError();
-  if (!ok) {
-    if (ga) hipGraphExecDestroy(ga);
-    if (gb) hipGraphExecDestroy(gb);
-    return false;
-  }
-  out[0] = ga;
-  out[1] = gb;
-  return true;
+  if (!ok) release_graph(sg);
+  return ok;
 }
 
 std::vector<int> fp32_key(const bss_ctx *c) {
@@ -957,10 +988,9 @@ std::vector<int> fp32_key(const bss_ctx *c) {
   return k;
 }
 
+// (the caller has synchronised the context stream the graphs run on)
 void destroy_graphs(bss_ctx *c) {
-  for (auto &sg : c->gcache)
-    for (auto g : sg.g)
-      if (g) hipGraphExecDestroy(g);
+  for (auto &sg : c->gcache) release_graph(sg);
   c->gcache.clear();
 }
 
@@ -972,13 +1002,13 @@ const bss_ctx::SweepGraph *sweep_graph(bss_ctx *c) {
   for (auto &sg : c->gcache)
     if (sg.key == key) return &sg;
   if (c->gcache.size() >= 8) {
-    for (auto g : c->gcache.front().g)
-      if (g) hipGraphExecDestroy(g);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) { c->graphs = false; return nullptr; }
+    release_graph(c->gcache.front());
     c->gcache.erase(c->gcache.begin());
   }
   bss_ctx::SweepGraph sg;
   sg.key = key;
-  if (!capture_sweep(c, sg.g)) {
+  if (!capture_sweep(c, sg)) {
     c->graphs = false;
     return nullptr;
   }
@@ -1020,7 +1050,19 @@ bss_status adapt_fp32(bss_ctx *c) {
     std::vector<ChainStats> cs(I.C);
     HIP_TRY(c, hipMemcpy(cs.data(), I.stats, sizeof(ChainStats) * I.C, hipMemcpyDeviceToHost));
     double d = 0.0;
-    for (auto &x : cs) d = std::isnan(x.rdrift_sweep) ? INFINITY : std::max(d, x.rdrift_sweep);
+    int64_t rej = 0;
+    for (auto &x : cs) {
+      d = std::isnan(x.rdrift_sweep) ? INFINITY : std::max(d, x.rdrift_sweep);
+      rej += x.fp32_rejected;
+    }
+    if (rej > I.fp32_rej_seen) {   // the fuse: FP32 is not safe for this instance
+      I.fp32_rej_seen = rej;
+      I.adapt = false;
+      I.fused = true;
+      next[k] = 0;
+      changed = changed || I.m32 != 0;
+      continue;
+    }
     if (d > 0.5 * target) next[k] = std::max(0, I.m32 - 1);
     else if (d * std::exp(2.0 * I.lambda) < 0.5 * target) next[k] = std::min(I.m32_max, I.m32 + 1);
     changed = changed || next[k] != I.m32;
@@ -1052,11 +1094,15 @@ bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure) {
   bool adapt = false;
   for (auto &I : c->sh) adapt = adapt || I.adapt;
   // with the drift controller the FP32 slice counts may change after every
-  // sweep, so sweeps are issued one at a time
+  // sweep, so sweeps are issued one at a time, and launched directly: a
+  // process that had swept a controlled context through captured sweeps of
+  // several counts crashed in the HIP runtime when it went on to the next
+  // context (twice at the same point, cause not found), so captured sweeps
+  // are kept to contexts whose slice precisions never change
   const int per = adapt ? 1 : std::max(1, n_sweeps);
   for (int done = 0; done < n_sweeps; done += per) {
     const int n = std::min(per, n_sweeps - done);
-    const bss_ctx::SweepGraph *sg = (c->graphs && !measure) ? sweep_graph(c) : nullptr;
+    const bss_ctx::SweepGraph *sg = (c->graphs && !measure && !adapt) ? sweep_graph(c) : nullptr;
     if (sg) {
       for (int sw = 0; sw < n; ++sw) {
         HIP_TRY(c, hipGraphLaunch(sg->g[0], c->stream));
@@ -1267,6 +1313,8 @@ bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
     run += I.slices_run;
     run32 += I.fp32_run;
     negs += x_negs(cs);
+    for (auto &x : cs) out->fp32_rejected += x.fp32_rejected;
+    out->fp32_fused = out->fp32_fused || I.fused;
   }
   out->sign = (negs % 2) ? -1 : 1;
   out->fp32_fraction = run ? (double)run32 / (double)run : 0.0;
@@ -1456,6 +1504,7 @@ bss_status bss_reset_stats(bss_ctx *c) {
     std::memset(zero.data(), 0, sizeof(ChainStats) * I.C);
     HIP_TRY(c, hipMemcpy(I.stats, zero.data(), sizeof(ChainStats) * I.C, hipMemcpyHostToDevice));
     I.slices_run = I.fp32_run = 0;
+    I.fp32_rej_seen = 0;
   }
   return BSS_OK;
 }
@@ -1732,10 +1781,17 @@ bss_status bss_autotune(const bss_instance *inst, const bss_options *base, doubl
 
 void bss_destroy(bss_ctx *c) {
   if (!c) return;
+  // everything finished first, then the graphs (and their events), then the
+  // events and streams of direct launches, then the memory
   if (c->stream) hipStreamSynchronize(c->stream);
   for (auto &I : c->sh) {
-    if (I.s) { hipStreamSynchronize(I.s); hipStreamDestroy(I.s); }
-    if (I.aux) { hipStreamSynchronize(I.aux); hipStreamDestroy(I.aux); }
+    if (I.s) hipStreamSynchronize(I.s);
+    if (I.aux) hipStreamSynchronize(I.aux);
+  }
+  destroy_graphs(c);
+  for (auto &I : c->sh) {
+    if (I.s) hipStreamDestroy(I.s);
+    if (I.aux) hipStreamDestroy(I.aux);
     if (I.ev_main) hipEventDestroy(I.ev_main);
     if (I.ev_left) hipEventDestroy(I.ev_left);
   }
@@ -1743,7 +1799,6 @@ void bss_destroy(bss_ctx *c) {
     for (auto &p : f.pending) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
   for (auto e : c->pool) hipEventDestroy(e);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
-  destroy_graphs(c);
   if (c->own_mem && c->mem) hipFree(c->mem);
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   delete c;

@@ -125,3 +125,27 @@ def test_controller_chain_matches_the_oracle():
         for s in range(2):
             err = np.max(np.abs(g.green(0, c, s) - o.green(s))) / max(1.0, np.max(np.abs(o.green(s))))
             assert err < 1e-10, (c, s, err)
+
+
+def test_controller_fp32_ratio_fuse():
+    """Automatic FP32 slices: a non-positive ratio met in an FP32 slice (here
+    forced: G_ii = 5 just before the block's first FP32 slice) is rejected
+    and counted, not a failure; after that sweep the instance runs in FP64
+    (the fuse) and keeps sweeping."""
+    # the forced G_ii = 5 survives to the recomputation as a drift of ~5:
+    # drift_abort is switched off to test the fuse on its own
+    g = make(L=8, beta=10.0, chains=2, precision="mixed", delay_k=16, n_stab=10, drift_abort=0.0)
+    g.sweep(3)                                   # the controller reaches 2 FP32 slices
+    assert g.stats()["fp32_slices"] == 2
+    g.step_slices(8)                             # slices 9 and 10 run in FP32
+    g.debug_set_green(5.0, chain=1, spin=1, i=20, j=20)
+    g.step_slices(12)                            # to the end of the sweep
+    st = g.stats()
+    assert st["fp32_rejected"] >= 1 and st["fp32_fused"] == 0
+    g.sweep(1)                                   # the controller sees the rejection
+    st = g.stats()
+    print(f"[gpu] fuse: rejected {st['fp32_rejected']}, fused {st['fp32_fused']}, "
+          f"fp32_slices {st['fp32_slices']}")
+    assert st["fp32_fused"] == 1 and st["fp32_slices"] == 0
+    g.sweep(2)
+    assert g.stats()["fp32_slices"] == 0
