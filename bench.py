@@ -45,7 +45,16 @@ HBM_PEAK = 8.0e12
 # (profiles/*_hbm_traffic.md), valid while the kernel's source file is the
 # one the counters were taken on (sha1 prefix); otherwise null.
 TRAFFIC = {
-    "dense": {},
+    "dense": {
+        "qr_udv": (5.350e8, "k_qr.hip", "7f1ff4059918"),
+        "qr_solve": (5.208e8, "k_qr.hip", "7f1ff4059918"),
+        "flip_f64": (1.531e8, "k_flip.hip", "f441bb0b7329"),
+        "flip_f32": (4.01e7, "k_flip.hip", "f441bb0b7329"),
+        # the FP64 NN GEMM kernel (wraps, block products and UDV products share it)
+        "wrap_f64": (1.141e8, "k_gemm.hip", "57c2c9444073"),
+        "gemm_f64": (1.141e8, "k_gemm.hip", "57c2c9444073"),
+        "wrap_f32": (4.41e7, "k_gemm.hip", "57c2c9444073"),
+    },
     "kronecker": {},
 }
 
