@@ -344,6 +344,52 @@ bss_status bss_green_from_field_noalloc(int32_t L, double U, double t, double be
 bss_status bss_debug_set_green(bss_ctx *c, int32_t inst, int32_t chain, int32_t spin, int32_t i, int32_t j,
                                double value);
 
+/* ------------------------------------------------------------------------
+ * Analysis of the sweep's output (host code, host buffers, synchronous; no
+ * GPU needed).  Readings where the paper is silent: cubic splines with
+ * not-a-knot ends; a least-squares polynomial in dtau^2 of order
+ * min(2, grids - 1); eq. (5) with e^{+i w_n tau}, w_n = (2n+1) pi / beta (the
+ * sign that agrees with eq. (6) under eq. (4)'s convention).  INVALID_ARG for
+ * sizes out of range, NULL pointers or non-finite inputs; NUMERICAL when a fit
+ * or an inverse does not exist. */
+
+/* Trotter elimination (paper Sec. 3, "Trotter bias" paragraph): the Green
+ * functions of n_grids >= 2 slice widths dtau[a] at one beta are aligned on
+ * the common grid tau_out[0..n_out) (values in [0, beta]) by cubic splines
+ * through their slice grids tau_l = l dtau[a], l = 0..Lambda_a, and
+ * extrapolated pointwise to dtau -> 0.  G[a]: (Lambda_a + 1) x n_cols values,
+ * row-major [l][col] (e.g. the rows of bss_measure_gtau_k).  out: n_out x
+ * n_cols, the constant term of each pointwise fit. */
+bss_status bss_trotter_extrapolate(int32_t n_grids, const double *dtau, double beta, const double *const *G,
+                                   int32_t n_cols, int32_t n_out, const double *tau_out, double *out);
+
+/* Matsubara transform of eq. (5): G(i w_n), n = 0..n_freq-1, of the cubic
+ * spline through (tau[i], G[i]), i = 0..n_tau-1 (tau increasing from 0 to
+ * beta), integrated exactly piece by piece.  out: 2 n_freq doubles (re, im). */
+bss_status bss_matsubara(int32_t n_tau, const double *tau, const double *G, double beta, int32_t n_freq,
+                         double *out_re_im);
+
+/* Dyson equation, eq. (6): Sigma_k(i w_n) = i w_n + mu - eps_k - 1/G_k(i w_n)
+ * for n = 0..n_freq-1; G and Sigma as (re, im) pairs. */
+bss_status bss_dyson(int32_t n_freq, double beta, double eps_k, double mu, const double *G_re_im,
+                     double *sigma_re_im);
+
+/* Finite-size extrapolation (paper Sec. 3, last paragraph): values
+ * [n_L][n_vals] (row-major; real and imaginary parts as separate values) of
+ * lattices L[0..n_L) (n_L >= 3) fitted against 1/L^2 by least-squares
+ * polynomials of first and second order.  value = the average of the two
+ * constant terms, err = |linear - quadratic|; lin, quad (nullable) receive
+ * the constant terms themselves.  All outputs n_vals doubles. */
+bss_status bss_finite_size_extrapolate(int32_t n_L, const int32_t *L, int32_t n_vals, const double *values,
+                                       double *value, double *err, double *lin, double *quad);
+
+/* Correlation length (paper Sec. 4, Fig. 5): least-squares fit of
+ * log|C(x)| = log A - x / xi over 1 <= x <= L/2, |C(x)| the average of
+ * |C(x, 0)| and |C(0, x)| of a spin correlation C[r], r = dx + L dy (as
+ * bss_measure_spin_corr reports it).  NUMERICAL if a value is 0 or the fit
+ * does not decay.  amplitude is nullable. */
+bss_status bss_correlation_length(int32_t L, const double *C, double *xi, double *amplitude);
+
 /* Release the context (NULL is allowed). */
 void bss_destroy(bss_ctx *c);
 

@@ -28,6 +28,8 @@ EXPORTS = [
     "bss_get_stats", "bss_save", "bss_load", "bss_destroy", "bss_status_string", "bss_last_error",
     "bss_get_profile", "bss_reset_profile", "bss_autotune", "bss_debug_set_green", "bss_green_from_field",
     "bss_green_from_field_noalloc", "bss_green_from_field_noalloc_limit",
+    "bss_trotter_extrapolate", "bss_matsubara", "bss_dyson", "bss_finite_size_extrapolate",
+    "bss_correlation_length",
 ]
 
 
@@ -111,6 +113,11 @@ def lib():
         L.bss_green_from_field.argtypes = [i32, dbl, dbl, dbl, dbl, i32, i32, vp, vp, vp]
         L.bss_green_from_field_noalloc.argtypes = [i32, dbl, dbl, dbl, dbl, i32, i32, vp, vp, vp]
         L.bss_green_from_field_noalloc_limit.argtypes = []
+        L.bss_trotter_extrapolate.argtypes = [i32, vp, dbl, vp, i32, i32, vp, vp]
+        L.bss_matsubara.argtypes = [i32, vp, vp, dbl, i32, vp]
+        L.bss_dyson.argtypes = [i32, dbl, dbl, dbl, vp, vp]
+        L.bss_finite_size_extrapolate.argtypes = [i32, vp, i32, vp, vp, vp, vp, vp]
+        L.bss_correlation_length.argtypes = [i32, vp, P(dbl), P(dbl)]
         L.bss_green_from_field_noalloc_limit.restype = sz
         L.bss_destroy.argtypes = [vp]
         L.bss_destroy.restype = None
@@ -348,3 +355,64 @@ def autotune(instance: dict, precision="fp64", drift_bound=1e-6, warmup_sweeps=4
     out = {f: getattr(res, f) for f, _ in TuneResult._fields_}
     out["precision"] = "mixed" if res.precision == PREC["mixed"] else "fp64"
     return out
+
+
+# ---------------------------------------------------------------------------
+# analysis of the sweep's output (host code of the library)
+
+def _host_check(st, what):
+    if st != BSS_OK:
+        raise BssError(st, f"{what}: {lib().bss_status_string(st).decode()}")
+
+
+def trotter_extrapolate(dtaus, Gs, beta, tau_out):
+    """bss_trotter_extrapolate: Gs[a] [Lambda_a + 1, n_cols] on the slice grid
+    of dtaus[a]; returns [len(tau_out), n_cols] at dtau -> 0."""
+    arrs = [np.ascontiguousarray(np.asarray(G, dtype=np.float64).reshape(len(G), -1)) for G in Gs]
+    n_cols = arrs[0].shape[1]
+    assert all(a.shape[1] == n_cols for a in arrs)
+    ptrs = (ctypes.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+    dt = np.ascontiguousarray(dtaus, dtype=np.float64)
+    to = np.ascontiguousarray(tau_out, dtype=np.float64)
+    out = np.zeros((len(to), n_cols))
+    _host_check(lib().bss_trotter_extrapolate(len(arrs), _ptr(dt), float(beta), ptrs, n_cols, len(to), _ptr(to),
+                                              _ptr(out)), "bss_trotter_extrapolate")
+    return out
+
+
+def matsubara(tau, G, beta, n_freq):
+    """bss_matsubara: complex G(i w_n), n = 0..n_freq-1."""
+    t = np.ascontiguousarray(tau, dtype=np.float64)
+    g = np.ascontiguousarray(G, dtype=np.float64)
+    out = np.zeros(2 * n_freq)
+    _host_check(lib().bss_matsubara(len(t), _ptr(t), _ptr(g), float(beta), n_freq, _ptr(out)), "bss_matsubara")
+    return out[0::2] + 1j * out[1::2]
+
+
+def dyson(beta, eps_k, mu, G_iw):
+    """bss_dyson: Sigma_k(i w_n) from complex G_k(i w_n)."""
+    g = np.ascontiguousarray(np.stack([np.real(G_iw), np.imag(G_iw)], axis=1).ravel())
+    out = np.zeros_like(g)
+    _host_check(lib().bss_dyson(len(G_iw), float(beta), float(eps_k), float(mu), _ptr(g), _ptr(out)), "bss_dyson")
+    return out[0::2] + 1j * out[1::2]
+
+
+def finite_size_extrapolate(Ls, values):
+    """bss_finite_size_extrapolate over real values [len(Ls), n]; returns
+    (value, err, lin, quad), each [n]."""
+    Larr = np.ascontiguousarray(Ls, dtype=np.int32)
+    v = np.ascontiguousarray(np.asarray(values, dtype=np.float64).reshape(len(Ls), -1))
+    n = v.shape[1]
+    outs = [np.zeros(n) for _ in range(4)]
+    _host_check(lib().bss_finite_size_extrapolate(len(Larr), _ptr(Larr), n, _ptr(v), *[_ptr(o) for o in outs]),
+                "bss_finite_size_extrapolate")
+    return tuple(outs)
+
+
+def correlation_length(L, C):
+    """bss_correlation_length: (xi, amplitude) of a spin correlation C[r]."""
+    c = np.ascontiguousarray(C, dtype=np.float64)
+    xi, A = ctypes.c_double(), ctypes.c_double()
+    _host_check(lib().bss_correlation_length(int(L), _ptr(c), ctypes.byref(xi), ctypes.byref(A)),
+                "bss_correlation_length")
+    return xi.value, A.value
