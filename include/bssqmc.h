@@ -205,8 +205,8 @@ bss_status bss_workspace_size(const bss_instance *inst, int32_t n_inst, const bs
                               size_t *bytes);
 
 /* Run n_sweeps full sweeps of every chain of every instance (asynchronous).
- * measure != 0: after each sweep accumulate double occupancy and G(tau_l, k)
- * from the fresh G(tau = 0).  STATE if an instance is not at slice 1. */
+ * measure != 0: after each sweep accumulate double occupancy, the spin
+ * correlation and G(tau_l, k) from the fresh G(tau = 0).  STATE if an instance is not at slice 1. */
 bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure);
 
 /* Advance every instance by n_slices slices (asynchronous); sweeps may end
@@ -223,6 +223,15 @@ bss_status bss_measure_gtau_k(bss_ctx *c, int32_t inst, double *mean, double *st
 
 /* Mean (and standard error) of D = (1/N) sum_i <n_i,up n_i,dn>. */
 bss_status bss_measure_double_occ(bss_ctx *c, int32_t inst, double *mean, double *stderr_out);
+
+/* Real-space spin correlation of Sec. 4 (Fig. 5), accumulated with the other
+ * observables: out[r] = C(r) = (1/N) sum_i <S^z_i S^z_{i+r}>, S^z = (n_up -
+ * n_dn)/2, r = dx + L dy with periodic wrap, evaluated per field by Wick's
+ * theorem from the fresh G(tau = 0).  len must equal N; mean and stderr_out
+ * are host arrays of len doubles (stderr_out may be NULL), errors as for
+ * bss_measure_gtau_k.  STATE if nothing was measured.  The correlation length
+ * follows from bss_correlation_length. */
+bss_status bss_measure_spin_corr(bss_ctx *c, int32_t inst, double *mean, double *stderr_out, int64_t len);
 
 /* Discard accumulated measurements. */
 bss_status bss_reset_measurements(bss_ctx *c);

@@ -23,7 +23,7 @@ FLAG_KRONECKER_HOPPING = 0x10
 # every entry point declared in include/bssqmc.h
 EXPORTS = [
     "bss_options_default", "bss_create", "bss_create_batch", "bss_workspace_size", "bss_sweep",
-    "bss_step_slices", "bss_measure_gtau_k", "bss_measure_double_occ", "bss_reset_measurements", "bss_reset_stats", "bss_synchronize",
+    "bss_step_slices", "bss_measure_gtau_k", "bss_measure_double_occ", "bss_measure_spin_corr", "bss_reset_measurements", "bss_reset_stats", "bss_synchronize",
     "bss_get_green", "bss_get_field", "bss_set_field", "bss_set_trace", "bss_get_trace",
     "bss_get_stats", "bss_save", "bss_load", "bss_destroy", "bss_status_string", "bss_last_error",
     "bss_get_profile", "bss_reset_profile", "bss_autotune", "bss_debug_set_green", "bss_green_from_field",
@@ -95,6 +95,7 @@ def lib():
         L.bss_step_slices.argtypes = [vp, i32]
         L.bss_measure_gtau_k.argtypes = [vp, i32, vp, vp, i64]
         L.bss_measure_double_occ.argtypes = [vp, i32, P(dbl), P(dbl)]
+        L.bss_measure_spin_corr.argtypes = [vp, i32, vp, vp, i64]
         L.bss_reset_measurements.argtypes = [vp]
         L.bss_reset_stats.argtypes = [vp]
         L.bss_synchronize.argtypes = [vp]
@@ -285,6 +286,12 @@ class Context:
         self._check(lib().bss_measure_double_occ(self._h, inst, ctypes.byref(m), ctypes.byref(e)),
                     "bss_measure_double_occ")
         return m.value, e.value
+
+    def spin_corr(self, inst=0):
+        n = self._params[inst]["N"]
+        mean, err = np.zeros(n), np.zeros(n)
+        self._check(lib().bss_measure_spin_corr(self._h, inst, _ptr(mean), _ptr(err), n), "bss_measure_spin_corr")
+        return mean, err
 
     def reset_measurements(self):
         self._check(lib().bss_reset_measurements(self._h), "bss_reset_measurements")

@@ -1,7 +1,11 @@
-// Measurement kernels (FP64): double occupancy and the momentum-resolved
-// time-displaced Green function, accumulated per chain in blocked bins.
+// Measurement kernels (FP64): double occupancy, the momentum-resolved
+// time-displaced Green function and the real-space spin correlation,
+// accumulated per chain in blocked bins.
 //
 //   D = (1/N) sum_i (1 - G_up,ii)(1 - G_dn,ii)        (Wick, spins decouple per field)
+//   C(r) = (1/N) sum_i <S^z_i S^z_{i+r}>,  S^z = (n_up - n_dn)/2  (paper Sec. 4, Fig. 5):
+//     per field <S^z_i S^z_j> = [m_i m_j + sum_s (delta_ij G_s,ii - G_s,ji G_s,ij)] / 4,
+//     m_i = <n_i,up> - <n_i,dn> = G_dn,ii - G_up,ii
 //   G(tau_l, k) = -1/2 sum_sigma (1/N) sum_ij cos(k.(r_i - r_j)) G_sigma,ij(tau_l, 0)
 // The second is evaluated through the lattice-averaged g(delta) =
 // (1/N) sum_i G_{i+delta, i}, then G(tau_l, k) = -1/2 sum_sigma sum_delta cos(k.delta) g(delta).
@@ -34,6 +38,12 @@ __global__ void k_meas_begin(MeasState ms, int chains) {
         for (int bin = 0; bin < ms.nbins / 2; ++bin)
           gb[bin * per_g + off] = gb[(2 * bin) * per_g + off] + gb[(2 * bin + 1) * per_g + off];
         for (int bin = ms.nbins / 2; bin < ms.nbins; ++bin) gb[bin * per_g + off] = 0.0;
+      }
+      double *sb = ms.sc + (long)c * ms.nbins_g * ms.sclen;
+      for (long off = threadIdx.x; off < ms.sclen; off += blockDim.x) {
+        for (int bin = 0; bin < ms.nbins / 2; ++bin)
+          sb[bin * ms.sclen + off] = sb[(2 * bin) * ms.sclen + off] + sb[(2 * bin + 1) * ms.sclen + off];
+        for (int bin = ms.nbins / 2; bin < ms.nbins; ++bin) sb[bin * ms.sclen + off] = 0.0;
       }
     }
     __syncthreads();
@@ -91,6 +101,26 @@ __global__ __launch_bounds__(256) void k_meas_gk(MeasState ms, const double *Gt,
     out[k] += -0.5 * s;
   }
 }
+// One chain per block: the local moments in LDS, then one displacement r
+// per thread summed over the sites i (j = i + r with periodic wrap).
+__global__ __launch_bounds__(256) void k_meas_sc(MeasState ms, const double *Gf, int L) {
+  extern __shared__ double mom[];   // [N] m_i = G_dn,ii - G_up,ii
+  const int N = L * L, c = blockIdx.x;
+  const double *gu = Gf + (2L * c) * N * N, *gd = gu + (long)N * N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) mom[i] = gd[(long)i * N + i] - gu[(long)i * N + i];
+  __syncthreads();
+  double *out = ms.sc + ((long)c * ms.nbins_g + (ms.nbins_g == 1 ? 0 : ms.cur[c])) * ms.sclen;
+  for (int r = threadIdx.x; r < N; r += blockDim.x) {
+    const int dx = r % L, dy = r / L;
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const int j = ((i % L) + dx) % L + L * (((i / L) + dy) % L);
+      s += mom[i] * mom[j] - gu[(long)j * N + i] * gu[(long)i * N + j] - gd[(long)j * N + i] * gd[(long)i * N + j];
+      if (j == i) s += gu[(long)i * N + i] + gd[(long)i * N + i];
+    }
+    out[r] += 0.25 * s / N;
+  }
+}
 }  // namespace
 
 hipError_t meas_begin(const MeasState &ms, int chains, hipStream_t s) {
@@ -103,6 +133,10 @@ hipError_t meas_end(const MeasState &ms, int chains, hipStream_t s) {
 }
 hipError_t meas_docc(const MeasState &ms, const double *Gf, int chains, int N, hipStream_t s) {
   hipLaunchKernelGGL(k_meas_docc, dim3(chains), dim3(256), 0, s, ms, Gf, N);
+  return hipGetLastError();
+}
+hipError_t meas_sc(const MeasState &ms, const double *Gf, int chains, int L, hipStream_t s) {
+  hipLaunchKernelGGL(k_meas_sc, dim3(chains), dim3(256), sizeof(double) * L * L, s, ms, Gf, L);
   return hipGetLastError();
 }
 hipError_t meas_gk(const MeasState &ms, const double *Gt, int chains, int L, int l, hipStream_t s) {

@@ -292,6 +292,8 @@ void layout_shard(Shard &I, bool fp64, Carver &cv) {
   I.ms.glen = (long)(I.Lam + 1) * I.N;
   I.ms.docc = cv.take<double>((size_t)I.C * NBINS);
   I.ms.gk = cv.take<double>((size_t)I.C * I.ms.nbins_g * I.ms.glen);
+  I.ms.sclen = I.N;
+  I.ms.sc = cv.take<double>((size_t)I.C * I.ms.nbins_g * I.ms.sclen);
   I.ms.count = cv.take<int64_t>(I.C);
   I.ms.binsize = cv.take<int64_t>(I.C);
   I.ms.cur = cv.take<int>(I.C);
@@ -660,6 +662,7 @@ struct Exec {
     }
     chk(meas_begin(I.ms, I.C, s));
     chk(meas_docc(I.ms, I.Gf, I.C, I.N, s));
+    chk(meas_sc(I.ms, I.Gf, I.C, I.L, s));
     chk(hipMemcpyAsync(I.Gt, I.Gf, sizeof(double) * I.mats * NN(), hipMemcpyDeviceToDevice, s));
     chk(meas_gk(I.ms, I.Gt, I.C, I.L, 0, s));
     for (int l = 1; l <= I.Lam; ++l) {
@@ -1331,20 +1334,26 @@ bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
 namespace {
 
 // per-chain measurement arrays of one instance, in chain order
-bss_status fetch_meas(bss_ctx *c, const UInst &U, std::vector<double> &docc, std::vector<double> &gk,
+// per-chain bins of one observable of an instance, in chain order: the double
+// occupancy ([C][NBINS]), G(tau, k) or C(r) ([C][nbins_g][len])
+enum Obs { OBS_DOCC, OBS_GK, OBS_SC };
+
+bss_status fetch_meas(bss_ctx *c, const UInst &U, Obs which, std::vector<double> &docc, std::vector<double> &gk,
                       std::vector<int64_t> &count, std::vector<int64_t> &binsize, size_t &glen) {
   const Shard &F = c->sh[U.first];
-  glen = (size_t)F.ms.glen;
+  glen = (size_t)(which == OBS_SC ? F.ms.sclen : F.ms.glen);
   const size_t gper = (size_t)F.ms.nbins_g * glen;
   docc.resize((size_t)U.C * NBINS);
-  gk.resize((size_t)U.C * gper);
+  gk.resize(which == OBS_DOCC ? 0 : (size_t)U.C * gper);
   count.resize(U.C);
   binsize.resize(U.C);
   for (int k = 0; k < U.count; ++k) {
     const Shard &I = c->sh[U.first + k];
     const size_t c0 = I.chain0;
     HIP_TRY(c, hipMemcpy(docc.data() + c0 * NBINS, I.ms.docc, sizeof(double) * I.C * NBINS, hipMemcpyDeviceToHost));
-    HIP_TRY(c, hipMemcpy(gk.data() + c0 * gper, I.ms.gk, sizeof(double) * I.C * gper, hipMemcpyDeviceToHost));
+    if (which != OBS_DOCC)
+      HIP_TRY(c, hipMemcpy(gk.data() + c0 * gper, which == OBS_SC ? I.ms.sc : I.ms.gk, sizeof(double) * I.C * gper,
+                           hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(count.data() + c0, I.ms.count, sizeof(int64_t) * I.C, hipMemcpyDeviceToHost));
     HIP_TRY(c, hipMemcpy(binsize.data() + c0, I.ms.binsize, sizeof(int64_t) * I.C, hipMemcpyDeviceToHost));
   }
@@ -1375,17 +1384,19 @@ void mean_err(const std::vector<std::vector<double>> &samples, const std::vector
   }
 }
 
-bss_status measure_common(bss_ctx *c, int32_t inst, bool gk_wanted, double *mean, double *err, int64_t len) {
+bss_status measure_common(bss_ctx *c, int32_t inst, Obs which, double *mean, double *err, int64_t len) {
   UInst *U;
   bss_status st = pick(c, inst, &U);
   if (st != BSS_OK) return st;
   if (!mean) return fail(c, BSS_E_INVALID_ARG, "mean is NULL");
-  if (gk_wanted && len != (int64_t)(U->Lam + 1) * U->N) return fail(c, BSS_E_INVALID_ARG, "len must be (Lambda+1)*N");
+  if (which == OBS_GK && len != (int64_t)(U->Lam + 1) * U->N) return fail(c, BSS_E_INVALID_ARG, "len must be (Lambda+1)*N");
+  if (which == OBS_SC && len != (int64_t)U->N) return fail(c, BSS_E_INVALID_ARG, "len must be N");
   if ((st = check_err(c)) != BSS_OK) return st;
+  const bool gk_wanted = which != OBS_DOCC;
   std::vector<double> docc, gk;
   std::vector<int64_t> count, binsize;
   size_t glen = 0;
-  if ((st = fetch_meas(c, *U, docc, gk, count, binsize, glen)) != BSS_OK) return st;
+  if ((st = fetch_meas(c, *U, which, docc, gk, count, binsize, glen)) != BSS_OK) return st;
   if (count[0] == 0) return fail(c, BSS_E_STATE, "no measurements accumulated");
   std::vector<std::vector<double>> samples;
   std::vector<double> weights;
@@ -1434,7 +1445,7 @@ const uint64_t CK_MAGIC = 0x32504B4353534221ull;
 size_t inst_ck_bytes(const bss_ctx *c, const UInst &U) {
   const Shard &F = c->sh[U.first];
   return 32 + (size_t)U.C * U.Lam * U.N + sizeof(ChainStats) * U.C + sizeof(double) * U.C * NBINS +
-         sizeof(double) * U.C * F.ms.nbins_g * F.ms.glen + 2 * sizeof(int64_t) * U.C;
+         sizeof(double) * U.C * F.ms.nbins_g * (F.ms.glen + F.ms.sclen) + 2 * sizeof(int64_t) * U.C;
 }
 
 // one per-chain section of the checkpoint: `per(I)` bytes per chain at `dev(I)`
@@ -1458,6 +1469,8 @@ bss_status ck_transfer(bss_ctx *c, const UInst &U, char *&p, bool save) {
   if ((st = ck_section(c, U, p, sizeof(ChainStats), [](Shard &I) { return (void *)I.stats; }, save)) != BSS_OK) return st;
   if ((st = ck_section(c, U, p, sizeof(double) * NBINS, [](Shard &I) { return (void *)I.ms.docc; }, save)) != BSS_OK) return st;
   if ((st = ck_section(c, U, p, gper, [](Shard &I) { return (void *)I.ms.gk; }, save)) != BSS_OK) return st;
+  const size_t sper = sizeof(double) * F.ms.nbins_g * F.ms.sclen;
+  if ((st = ck_section(c, U, p, sper, [](Shard &I) { return (void *)I.ms.sc; }, save)) != BSS_OK) return st;
   if ((st = ck_section(c, U, p, sizeof(int64_t), [](Shard &I) { return (void *)I.ms.count; }, save)) != BSS_OK) return st;
   return ck_section(c, U, p, sizeof(int64_t), [](Shard &I) { return (void *)I.ms.binsize; }, save);
 }
@@ -1467,11 +1480,15 @@ bss_status ck_transfer(bss_ctx *c, const UInst &U, char *&p, bool save) {
 extern "C" {
 
 bss_status bss_measure_gtau_k(bss_ctx *c, int32_t inst, double *mean, double *err, int64_t len) {
-  return measure_common(c, inst, true, mean, err, len);
+  return measure_common(c, inst, OBS_GK, mean, err, len);
 }
 
 bss_status bss_measure_double_occ(bss_ctx *c, int32_t inst, double *mean, double *err) {
-  return measure_common(c, inst, false, mean, err, 1);
+  return measure_common(c, inst, OBS_DOCC, mean, err, 1);
+}
+
+bss_status bss_measure_spin_corr(bss_ctx *c, int32_t inst, double *mean, double *err, int64_t len) {
+  return measure_common(c, inst, OBS_SC, mean, err, len);
 }
 
 bss_status bss_reset_measurements(bss_ctx *c) {
@@ -1481,6 +1498,7 @@ bss_status bss_reset_measurements(bss_ctx *c) {
   for (auto &I : c->sh) {
     HIP_TRY(c, hipMemset(I.ms.docc, 0, sizeof(double) * I.C * NBINS));
     HIP_TRY(c, hipMemset(I.ms.gk, 0, sizeof(double) * I.C * I.ms.nbins_g * I.ms.glen));
+    HIP_TRY(c, hipMemset(I.ms.sc, 0, sizeof(double) * I.C * I.ms.nbins_g * I.ms.sclen));
     HIP_TRY(c, hipMemset(I.ms.count, 0, sizeof(int64_t) * I.C));
     std::vector<int64_t> ones(I.C, 1);
     HIP_TRY(c, hipMemcpy(I.ms.binsize, ones.data(), sizeof(int64_t) * I.C, hipMemcpyHostToDevice));

@@ -7,7 +7,8 @@
   its automatic delay depth and block length, in one batch): one free-running
   sweep against the oracle chain;
 - the measurement at U = 2 with several chains and measured sweeps: the
-  library's means and standard errors of G(tau_l, k) and D against the same
+  library's means and standard errors of G(tau_l, k), D and the spin
+  correlation C(r) against the same
   estimators formed from the oracle's per-sweep measurements of the same
   chains.
 """
@@ -16,6 +17,7 @@ import pytest
 
 import oracle
 import paper_1504_05090_amd as bss
+from oracle import analysis as an
 from paper_1504_05090_amd.workloads import BASE_SEED
 
 pytestmark = pytest.mark.gpu
@@ -84,33 +86,36 @@ def test_multigrid_grid_at_beta20():
 
 
 def oracle_estimates(L, U, beta, dtau, n_stab, chains, warm, meas):
-    """Per-chain means over `meas` measured sweeps (after `warm`) of D and
-    G(tau_l, k), then the library's estimators: the mean over all
-    measurements and the standard error over per-chain means."""
-    d_means, g_means = [], []
+    """Per-chain means over `meas` measured sweeps (after `warm`) of D,
+    G(tau_l, k) and the spin correlation C(r) (from the same fresh G at
+    slice 1), then the library's estimators: the mean over all measurements
+    and the standard error over per-chain means."""
+    d_means, g_means, c_means = [], [], []
     for c in range(chains):
         o = oracle.Chain(L, U, T, beta, dtau, BASE_SEED, 0, c, n_stab)
         o.sweep(warm)
-        ds, gs = [], []
+        ds, gs, cs = [], [], []
         for _ in range(meas):
             o.sweep(1)
             d, gk = o.measure()
             ds.append(d)
             gs.append(gk)
+            cs.append(an.spin_correlation(o.fresh_green(1, 0), o.fresh_green(1, 1), L))
         d_means.append(np.mean(ds))
         g_means.append(np.mean(gs, axis=0))
-    d_means, g_means = np.array(d_means), np.array(g_means)
+        c_means.append(np.mean(cs, axis=0))
+    d_means, g_means, c_means = np.array(d_means), np.array(g_means), np.array(c_means)
     n = chains
-    return (d_means.mean(), d_means.std(ddof=1) / np.sqrt(n),
-            g_means.mean(axis=0), g_means.std(axis=0, ddof=1) / np.sqrt(n))
+    se = lambda x: x.std(axis=0, ddof=1) / np.sqrt(n)
+    return (d_means.mean(), se(d_means), g_means.mean(axis=0), se(g_means), c_means.mean(axis=0), se(c_means))
 
 
 @pytest.mark.parametrize("L,beta,n_stab,chains,warm,meas", [(8, 10.0, 10, 3, 1, 3), (12, 10.0, 5, 2, 0, 1)])
 def test_measurement_at_u2_against_oracle(L, beta, n_stab, chains, warm, meas):
-    """U = 2: G(tau_l, k) (stable time-displaced G through several blocks)
-    and D, their means and standard errors over chains, against the oracle's
-    per-sweep measurements of the same chains: means to 1e-10 (G) and 1e-12
-    (D), errors to 1e-9 and 1e-11."""
+    """U = 2: G(tau_l, k) (stable time-displaced G through several blocks),
+    D and the spin correlation C(r), their means and standard errors over
+    chains, against the oracle's per-sweep measurements of the same chains:
+    means to 1e-10 (G), 1e-12 (D, C), errors to 1e-9, 1e-11, 1e-11."""
     U, dtau = 2.0, 0.5
     print(f"[gpu] measurement L={L} beta={beta} n_stab={n_stab} chains={chains} {warm}+{meas} sweeps", flush=True)
     g = bss.Context([dict(L=L, U=U, t=T, beta=beta, dtau=dtau, seed=BASE_SEED, n_chains=chains)],
@@ -119,12 +124,21 @@ def test_measurement_at_u2_against_oracle(L, beta, n_stab, chains, warm, meas):
     g.sweep(meas, measure=True)
     d, de = g.double_occ()
     gm, ge = g.gtau_k()
-    od, ode, ogm, oge = oracle_estimates(L, U, beta, dtau, n_stab, chains, warm, meas)
+    cm, ce = g.spin_corr()
+    od, ode, ogm, oge, ocm, oce = oracle_estimates(L, U, beta, dtau, n_stab, chains, warm, meas)
     print(f"[gpu] D = {d:.12f} +- {de:.3e} (oracle {od:.12f} +- {ode:.3e}); "
           f"max|dG(tau,k)| {np.max(np.abs(gm - ogm)):.3e}, max|d err| {np.max(np.abs(ge - oge)):.3e}")
     assert abs(d - od) < 1e-12 and abs(de - ode) < 1e-11
     assert np.max(np.abs(gm - ogm)) < 1e-10
     assert np.max(np.abs(ge - oge)) < 1e-9
+    print(f"[gpu] C(0) = {cm[0]:.12f}, C(1) = {cm[1]:.12f}; max|dC| {np.max(np.abs(cm - ocm)):.3e}, "
+          f"max|d err| {np.max(np.abs(ce - oce)):.3e}")
+    assert np.max(np.abs(cm - ocm)) < 1e-12 and np.max(np.abs(ce - oce)) < 1e-11
+    assert cm[1] < 0 < cm[0]   # antiferromagnetic neighbours at half filling
+    xi, A = bss.correlation_length(L, cm)
+    oxi, oA = an.correlation_length(cm, L)
+    print(f"[gpu] xi = {xi:.6f} (oracle fit {oxi:.6f})")
+    assert abs(xi - oxi) < 1e-10 * abs(oxi) and abs(A - oA) < 1e-10 * abs(oA)
 
 
 GOLDEN_L16 = "tests/golden/field_L16_U2_b20_dt0.5_w20.npy"
@@ -176,3 +190,25 @@ def test_green_from_field_argument_errors():
     with pytest.raises(bss.BssError) as e:
         bss.green_from_field(4, 2.0, T, 4.1, 0.5, 4, 1, f)          # beta / dtau not integral
     assert e.value.status == bss.BSS_E_INVALID_ARG
+
+
+def test_spin_correlation_u0_and_single_chain_bins():
+    """U = 0 (the field drops out, G is the free one for every field): the
+    library's C(r) equals the closed form of the free lattice, C(0) = 1/8 and
+    C(r) = -G_0r G_r0 / 2, for one chain binned over 40 measured sweeps
+    (bin merging exercised: more measurements than bins); its error is zero
+    to rounding."""
+    L, beta, dtau = 6, 4.0, 0.5
+    print("[gpu] spin correlation U=0 6x6, 40 measured sweeps", flush=True)
+    g = bss.Context([dict(L=L, U=0.0, t=T, beta=beta, dtau=dtau, seed=BASE_SEED, n_chains=1)], precision="fp64",
+                    delay_k=8, n_stab=4)
+    g.sweep(40, measure=True)
+    cm, ce = g.spin_corr()
+    o = oracle.Chain(L, 0.0, T, beta, dtau, BASE_SEED, 0, 0, 1)
+    G0 = o.fresh_green(1, 0)
+    ref = an.spin_correlation(G0, G0, L)
+    print(f"[gpu] max|C - free| {np.max(np.abs(cm - ref)):.3e}, max err {np.max(ce):.3e}")
+    assert abs(cm[0] - 0.125) < 1e-12
+    assert np.max(np.abs(cm - ref)) < 1e-12 and np.max(ce) < 1e-12
+    for r in range(1, L * L):
+        assert abs(cm[r] + 0.5 * G0[0, r] * G0[r, 0]) < 1e-12
