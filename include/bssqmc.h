@@ -399,6 +399,33 @@ bss_status bss_finite_size_extrapolate(int32_t n_L, const int32_t *L, int32_t n_
  * does not decay.  amplitude is nullable. */
 bss_status bss_correlation_length(int32_t L, const double *C, double *xi, double *amplitude);
 
+/* Maximum-entropy spectral function (paper Sec. 3, Trotter-bias paragraph,
+ * and eq. (4)), used there only to give back a smooth G(tau) through
+ * bss_mem_green.  Readings where the paper is silent: A lives on the
+ * increasing grid omega[0..n_omega) with trapezoid weights q_j, so eq. (4)
+ * reads G(tau_i) = -sum_j q_j A_j e^{-w_j tau_i} / (1 + e^{-w_j beta});
+ * chi^2 = sum_i ((G_i(A) - G[i]) / sigma[i])^2 (one standard error per tau
+ * point, no covariance); the entropy is S = sum_j q_j (A_j - m_j -
+ * A_j ln(A_j / m_j)) relative to the default model m = model[j] > 0; A
+ * minimises chi^2/2 - alpha S.  alpha > 0: that alpha; alpha <= 0: the
+ * historic alpha, where chi^2 = n_tau, searched in [1e-8, 1e12].
+ * Inputs: n_tau >= 2 points tau[i] in [0, beta] with data G[i] and errors
+ * sigma[i] > 0; n_omega >= 2 grid points.  Outputs: A (n_omega doubles);
+ * alpha_out, chi2_out (nullable) the alpha used and the chi^2 reached.
+ * INVALID_ARG for bad sizes, NULL pointers, non-finite or out-of-range
+ * inputs; NUMERICAL if the minimisation does not converge, if A would leave
+ * the double range (alpha too small for the data), or if the historic alpha
+ * does not exist inside the search range (chi^2 stays above n_tau). */
+bss_status bss_mem_spectrum(int32_t n_tau, const double *tau, const double *G, const double *sigma, double beta,
+                            int32_t n_omega, const double *omega, const double *model, double alpha, double *A,
+                            double *alpha_out, double *chi2_out);
+
+/* eq. (4) on the grid of bss_mem_spectrum: G_out[i] = -sum_j q_j A_j
+ * e^{-w_j tau_i} / (1 + e^{-w_j beta}) for n_tau >= 1 points tau[i] in
+ * [0, beta]; the smooth G(tau) of a maximum-entropy spectrum. */
+bss_status bss_mem_green(double beta, int32_t n_omega, const double *omega, const double *A, int32_t n_tau,
+                         const double *tau, double *G_out);
+
 /* Release the context (NULL is allowed). */
 void bss_destroy(bss_ctx *c);
 

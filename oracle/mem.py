@@ -97,10 +97,13 @@ class Problem:
         A > 0; the Newton system is solved in the variables A^{-1/2} dA,
         where it is well scaled.  Once the Newton decrement -g.dA (twice
         the predicted decrease of Q) is below 1e-10 |Q|, the iteration is in
-        its quadratic phase: one more full step brings it to rounding level,
-        and that is the result."""
+        its quadratic phase and takes full steps until no component of A
+        changes by more than 1e-8 of itself, which leaves every component at
+        the rounding floor of the gradient (the decrement alone weighs
+        components by their curvature and would leave small A_j behind)."""
         A = self.m.copy() if A0 is None else np.array(A0, dtype=float)
         Qa = self.Q(A, alpha)
+        quadratic = False
         for _ in range(max_iter):
             if not np.min(A) > 1e-290:
                 raise RuntimeError("MEM oracle: A underflows (alpha too small for these data)")
@@ -108,8 +111,15 @@ class Problem:
             D = np.sqrt(A)
             dA = D * np.linalg.solve(D[:, None] * self.hessian(A, alpha) * D[None, :], -D * g)
             dec = -float(g @ dA)
-            if dec <= 1e-10 * max(1.0, abs(Qa)):
-                return A + dA if np.all(A + dA > 0) else A
+            quadratic = quadratic or dec <= 1e-10 * max(1.0, abs(Qa))
+            if quadratic:
+                if not np.all(A + dA > 0):
+                    raise RuntimeError("MEM oracle: full step leaves A > 0 in the quadratic phase")
+                A = A + dA
+                if np.max(np.abs(dA) / A) <= 1e-8:
+                    return A
+                Qa = self.Q(A, alpha)
+                continue
             t = 1.0
             neg = dA < 0
             if np.any(neg):
@@ -128,8 +138,8 @@ class Problem:
 
 def spectrum(tau, G, sigma, beta, w, m, alpha=None, alpha_range=(1e-8, 1e12)):
     """A(w) by maximum entropy.  alpha > 0: that alpha; None: the historic
-    alpha with chi^2(A) = len(tau), bracketed by decades from alpha = 1
-    inside alpha_range.  Returns (A, alpha, chi^2)."""
+    alpha with chi^2(A) = len(tau), bracketed by decades downwards from the
+    top of alpha_range (chi^2 grows with alpha).  Returns (A, alpha, chi^2)."""
     P = Problem(tau, G, sigma, beta, w, m)
     if alpha is not None:
         A = P.solve(alpha)
@@ -139,18 +149,15 @@ def spectrum(tau, G, sigma, beta, w, m, alpha=None, alpha_range=(1e-8, 1e12)):
     def f(la):
         return P.chi2(P.solve(np.exp(la))) - n
 
-    lmin, lmax, dec = np.log(alpha_range[0]), np.log(alpha_range[1]), np.log(10.0)
-    lo = hi = 0.0
-    if f(0.0) < 0:
-        while f(hi) < 0:
-            lo, hi = hi, hi + dec
-            if hi > lmax:
-                raise RuntimeError("chi^2 = n is not reached inside the alpha range")
-    else:
-        while f(lo) >= 0:
-            lo, hi = lo - dec, lo
-            if lo < lmin:
-                raise RuntimeError("chi^2 = n is not reached inside the alpha range")
+    lmin, dec = np.log(alpha_range[0]), np.log(10.0)
+    hi = np.log(alpha_range[1])
+    if f(hi) < 0:
+        raise RuntimeError("chi^2 < n already at the largest alpha")
+    lo = hi - dec
+    while f(lo) >= 0:
+        hi, lo = lo, lo - dec
+        if lo < lmin:
+            raise RuntimeError("chi^2 = n is not reached inside the alpha range")
     la = brentq(f, lo, hi, xtol=1e-13, rtol=1e-14)
     A = P.solve(np.exp(la))
     return A, float(np.exp(la)), P.chi2(A)

@@ -29,7 +29,7 @@ EXPORTS = [
     "bss_get_profile", "bss_reset_profile", "bss_autotune", "bss_debug_set_green", "bss_green_from_field",
     "bss_green_from_field_noalloc", "bss_green_from_field_noalloc_limit",
     "bss_trotter_extrapolate", "bss_matsubara", "bss_dyson", "bss_finite_size_extrapolate",
-    "bss_correlation_length",
+    "bss_correlation_length", "bss_mem_spectrum", "bss_mem_green",
 ]
 
 
@@ -119,6 +119,8 @@ def lib():
         L.bss_dyson.argtypes = [i32, dbl, dbl, dbl, vp, vp]
         L.bss_finite_size_extrapolate.argtypes = [i32, vp, i32, vp, vp, vp, vp, vp]
         L.bss_correlation_length.argtypes = [i32, vp, P(dbl), P(dbl)]
+        L.bss_mem_spectrum.argtypes = [i32, vp, vp, vp, dbl, i32, vp, vp, dbl, vp, P(dbl), P(dbl)]
+        L.bss_mem_green.argtypes = [dbl, i32, vp, vp, i32, vp, vp]
         L.bss_green_from_field_noalloc_limit.restype = sz
         L.bss_destroy.argtypes = [vp]
         L.bss_destroy.restype = None
@@ -423,3 +425,28 @@ def correlation_length(L, C):
     _host_check(lib().bss_correlation_length(int(L), _ptr(c), ctypes.byref(xi), ctypes.byref(A)),
                 "bss_correlation_length")
     return xi.value, A.value
+
+
+def mem_spectrum(tau, G, sigma, beta, omega, model, alpha=None):
+    """bss_mem_spectrum: (A on omega, alpha, chi^2); alpha None = historic."""
+    t, g, sg = (np.ascontiguousarray(x, dtype=np.float64) for x in (tau, G, sigma))
+    w, m = (np.ascontiguousarray(x, dtype=np.float64) for x in (omega, model))
+    if not (len(t) == len(g) == len(sg)) or len(w) != len(m):
+        raise ValueError("tau, G, sigma and omega, model must have matching lengths")
+    A = np.zeros(len(w))
+    a, c = ctypes.c_double(), ctypes.c_double()
+    _host_check(lib().bss_mem_spectrum(len(t), _ptr(t), _ptr(g), _ptr(sg), float(beta), len(w), _ptr(w), _ptr(m),
+                                       0.0 if alpha is None else float(alpha), _ptr(A), ctypes.byref(a),
+                                       ctypes.byref(c)), "bss_mem_spectrum")
+    return A, a.value, c.value
+
+
+def mem_green(beta, omega, A, tau):
+    """bss_mem_green: eq. (4) of the spectrum A on omega at the points tau."""
+    w, a, t = (np.ascontiguousarray(x, dtype=np.float64) for x in (omega, A, tau))
+    if len(w) != len(a):
+        raise ValueError("omega and A must have the same length")
+    out = np.zeros(len(t))
+    _host_check(lib().bss_mem_green(float(beta), len(w), _ptr(w), _ptr(a), len(t), _ptr(t), _ptr(out)),
+                "bss_mem_green")
+    return out

@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbssqmc.so")
 
 SOURCES = ["k_gemm.hip", "k_hop.hip", "k_setup.hip", "k_flip.hip", "k_linalg.hip", "k_qr.hip", "k_measure.hip",
-           "green.hip", "green_static.hip", "runtime.cpp", "analysis.cpp"]
+           "green.hip", "green_static.hip", "runtime.cpp", "analysis.cpp", "mem.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
