@@ -215,8 +215,8 @@ def run_batch(bss, insts, steps, warmup, flags):
     ctx.synchronize()
     ms = timed_sweeps(ctx, stream, steps)
     upd = sum(d["n_chains"] * d["L"] ** 2 * int(round(d["beta"] / d["dtau"])) for d in insts)
-    params = [dict(L=insts[j]["L"], dtau=insts[j]["dtau"], **{q: ctx.params(j)[q] for q in ("delay_k", "n_stab")})
-              for j in range(len(insts))]
+    params = [dict(L=insts[j]["L"], dtau=insts[j]["dtau"], tuned=bool(insts[j].get("tuned", False)),
+                   **{q: ctx.params(j)[q] for q in ("delay_k", "n_stab")}) for j in range(len(insts))]
     graph = ctx.stats(0)["sweep_graph"]
     del ctx
     return upd * steps / (ms / 1e3), ms / steps, graph, params
@@ -297,6 +297,7 @@ def main():
         sys.exit(2)
 
     import paper_1504_05090_amd as bss
+    from paper_1504_05090_amd import tuning
     from paper_1504_05090_amd.workloads import BASE_SEED, CONFIGS, T_HOP
 
     if args.calibrate_copy:
@@ -417,12 +418,20 @@ def main():
         c3 = CONFIGS["C3"]
         insts = [dict(L=q["L"], U=q["U"], t=T_HOP, beta=q["beta"], dtau=q["dtau"], seed=BASE_SEED,
                       n_chains=c3["chains"]) for q in c3["instances"]]
-        v_graph, ms_graph, used_graph, params = run_batch(bss, insts, 5, 3, 0)
-        v_direct, ms_direct, _, _ = run_batch(bss, insts, 5, 3, bss.FLAG_NO_GRAPH)
+        # per-instance delay depth and block length from the table bss_autotune
+        # wrote for this device (paper_1504_05090_amd/tuning_<arch>.json)
+        tinsts = tuning.apply(insts, "fp64")
+        v_graph, ms_graph, used_graph, params = run_batch(bss, tinsts, 5, 3, 0)
+        v_direct, ms_direct, _, _ = run_batch(bss, tinsts, 5, 3, bss.FLAG_NO_GRAPH)
+        v_auto, ms_auto, _, _ = run_batch(bss, insts, 5, 3, 0)
         batch = {"workload": "16 instances L in {6,8,10,12} x dtau in {0.4,0.5,0.625,0.8}, U=2, beta=20, "
                              "32 chains each, FP64", "value": v_graph, "unit": "updates/s",
-                 "ms_per_step": ms_graph, "sweep_graph": used_graph, "direct_launch_value": v_direct,
-                 "direct_launch_ms_per_step": ms_direct, "instances": params}
+                 "ms_per_step": ms_graph, "sweep_graph": used_graph,
+                 "parameters": f"tuned: {sum(p['tuned'] for p in params)} of {len(params)} instances from "
+                               f"tuning_{tuning.device_arch()}.json (bss_autotune), the rest automatic",
+                 "direct_launch_value": v_direct, "direct_launch_ms_per_step": ms_direct,
+                 "automatic_parameters_ms_per_step": ms_auto, "automatic_parameters_value": v_auto,
+                 "instances": params}
         print(f"[bench] batch: {batch}", file=sys.stderr, flush=True)
 
     # 8. the cpu_baseline leg: the oracle on the host, and the sampled check

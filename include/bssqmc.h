@@ -137,12 +137,18 @@ typedef struct {
                             0 = 1e-3                                              */
 } bss_options;
 
-/* One (L, U, t, beta, dtau) instance with its chains. */
+/* One (L, U, t, beta, dtau) instance with its chains.  delay_k and n_stab,
+ * when > 0, set this instance's delay depth (1..32) and block length in
+ * place of the options' values (0: the options' value, and when that is 0
+ * too the automatic one), so that a batch can run each instance with its own
+ * tuned parameters (for instance those bss_autotune found for it). */
 typedef struct {
   int32_t L;
   double U, t, beta, dtau;
   uint64_t seed;         /* chain c uses Philox key (seed + c, instance index)     */
   int32_t n_chains;
+  int32_t delay_k;       /* 0 or 1..32                                             */
+  int32_t n_stab;        /* 0 or >= 1 (clamped to Lambda)                          */
 } bss_instance;
 
 typedef struct {
@@ -302,9 +308,13 @@ typedef struct {
  * candidate (delay_k, n_stab, fp32_slices) is loaded with those fields and
  * timed over trial_sweeps; the fastest whose relative wrap drift (as in
  * bss_stats.drift_rel_max) stays <= drift_bound is returned.  The search
- * takes n_stab in {2, 3, 4, 5, 6, 8, 10, 12, 16, 20} (at most Lambda) at the
- * automatic delay depth, then delay_k from three depths suited to N, then
- * (precision MIXED) fp32_slices = 1, 2, ... until the bound fails.  Other
+ * takes n_stab in {2, 3, 4, 5, 6, 8, 10, 12, 16, 20} (at most Lambda, and
+ * only block lengths whose product of slices has a condition estimate
+ * e^{n_stab (2 lambda + 8 t dtau)} <= 1e12, the range where the recomputed G
+ * is checked against the exact one to 1e-10) at the automatic delay depth,
+ * then delay_k from three depths suited to N, then (precision MIXED)
+ * fp32_slices = 1, 2, ... until the bound fails.  The instance's own
+ * delay_k and n_stab are ignored.  Other
  * fields of *base (precision, flags other than tracing) are kept.  Allocates
  * and frees its own trial contexts on the current device; synchronous.
  * INVALID_ARG: NULL pointers, drift_bound <= 0, warmup_sweeps < 0,

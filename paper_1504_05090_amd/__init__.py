@@ -43,7 +43,15 @@ class Options(ctypes.Structure):
 
 class Instance(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("U", ctypes.c_double), ("t", ctypes.c_double), ("beta", ctypes.c_double),
-                ("dtau", ctypes.c_double), ("seed", ctypes.c_uint64), ("n_chains", ctypes.c_int32)]
+                ("dtau", ctypes.c_double), ("seed", ctypes.c_uint64), ("n_chains", ctypes.c_int32),
+                ("delay_k", ctypes.c_int32), ("n_stab", ctypes.c_int32)]
+
+
+def _instance(d: dict) -> Instance:
+    """bss_instance from a dict (L, U, t, beta, dtau, seed, n_chains and the
+    optional per-instance delay_k, n_stab)."""
+    return Instance(int(d["L"]), float(d["U"]), float(d.get("t", 0.25)), float(d["beta"]), float(d["dtau"]),
+                    int(d["seed"]), int(d["n_chains"]), int(d.get("delay_k", 0)), int(d.get("n_stab", 0)))
 
 
 class Stats(ctypes.Structure):
@@ -178,8 +186,7 @@ class Context:
         L = lib()
         arr = (Instance * len(instances))()
         for n, d in enumerate(instances):
-            arr[n] = Instance(int(d["L"]), float(d["U"]), float(d.get("t", 0.25)), float(d["beta"]),
-                              float(d["dtau"]), int(d["seed"]), int(d["n_chains"]))
+            arr[n] = _instance(d)
         self._inst = arr
         self.n_inst = len(instances)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
@@ -353,8 +360,7 @@ def autotune(instance: dict, precision="fp64", drift_bound=1e-6, warmup_sweeps=4
     if not torch.cuda.is_available():
         raise BssError(BSS_E_DEVICE, "no GPU visible: the BSS-QMC library runs on gfx950 only")
     d = instance
-    inst = Instance(int(d["L"]), float(d["U"]), float(d.get("t", 0.25)), float(d["beta"]), float(d["dtau"]),
-                    int(d["seed"]), int(d["n_chains"]))
+    inst = _instance(d)
     opt = make_options(precision, flags=flags)
     res = TuneResult()
     st = lib().bss_autotune(ctypes.byref(inst), ctypes.byref(opt), float(drift_bound), int(warmup_sweeps),

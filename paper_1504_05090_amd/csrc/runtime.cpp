@@ -208,6 +208,8 @@ bool valid_instance(const bss_instance &in, std::string &why, bss_status &code) 
   if (lam < 1 || std::fabs(r - lam) > 1e-9 * r) { why = "beta/dtau must be an integer"; return false; }
   if (in.n_chains < 1) { why = "n_chains must be >= 1"; return false; }
   if (in.n_chains > 32767) { why = "n_chains must be <= 32767"; return false; }
+  if (in.delay_k < 0 || in.delay_k > 32) { why = "delay_k must be in 0..32"; return false; }
+  if (in.n_stab < 0) { why = "n_stab must be >= 0"; return false; }
   code = BSS_E_UNSUPPORTED;
   if (in.L % 2) { why = "odd L is not supported (periodic odd lattices are not bipartite)"; return false; }
   if ((long)in.L * in.L > NMAX) { why = "N = L^2 > 512 is not supported"; return false; }
@@ -316,8 +318,9 @@ bool resolve(const bss_instance *in, int n, const bss_options &opt, std::vector<
     I.Lam = (int)std::lround(I.beta / I.dtau);
     I.Ctot = in[i].n_chains; I.seed = in[i].seed; I.inst = i;
     I.lambda = std::acosh(std::exp(0.5 * I.dtau * I.U));
-    I.k = opt.delay_k > 0 ? opt.delay_k : auto_k(I.N);
-    I.n_stab = opt.n_stab > 0 ? opt.n_stab : auto_nstab(I.U, I.t, I.dtau);
+    // the instance's own setting, else the options', else automatic
+    I.k = in[i].delay_k > 0 ? in[i].delay_k : (opt.delay_k > 0 ? opt.delay_k : auto_k(I.N));
+    I.n_stab = in[i].n_stab > 0 ? in[i].n_stab : (opt.n_stab > 0 ? opt.n_stab : auto_nstab(I.U, I.t, I.dtau));
     I.n_stab = std::min(I.n_stab, I.Lam);
     I.nb = (I.Lam + I.n_stab - 1) / I.n_stab;
     if (opt.precision == BSS_PREC_MIXED) {
@@ -1656,8 +1659,10 @@ struct Trial {
 
 // one candidate: fresh context, fields from the checkpoint, one untimed sweep
 // (it captures the graph), then trial sweeps timed with events
-bss_status run_trial(const bss_instance &in, bss_options o, const std::vector<char> &ck, int trials, double bound,
+bss_status run_trial(const bss_instance &in0, bss_options o, const std::vector<char> &ck, int trials, double bound,
                      Trial &t) {
+  bss_instance in = in0;
+  in.delay_k = in.n_stab = 0;   // the options below decide
   o.delay_k = t.k;
   o.n_stab = t.ns;
   o.fp32_slices = t.m32;
@@ -1724,7 +1729,9 @@ bss_status bss_autotune(const bss_instance *inst, const bss_options *base, doubl
     o0.workspace = nullptr;
     o0.workspace_bytes = 0;
     bss_ctx *c = nullptr;
-    bss_status st = create_impl(inst, 1, &o0, &c);
+    bss_instance in0 = *inst;
+    in0.delay_k = in0.n_stab = 0;   // the options above decide
+    bss_status st = create_impl(&in0, 1, &o0, &c);
     if (st != BSS_OK) return st;
     size_t n = 0;
     st = bss_sweep(c, warmup_sweeps, 0);
@@ -1750,12 +1757,18 @@ bss_status bss_autotune(const bss_instance *inst, const bss_options *base, doubl
     if (!have || better(t, best)) { best = t; have = true; }
     return BSS_OK;
   };
-  // 1. block length, FP64 slices only
+  // 1. block length, FP64 slices only, up to a block condition estimate of
+  // 1e12 (log cond of one slice: 2 lambda + 8 t dtau)
   const int ns_list[] = {2, 3, 4, 5, 6, 8, 10, 12, 16, 20};
+  const double per = 2.0 * std::acosh(std::exp(0.5 * inst->dtau * inst->U)) + 8.0 * inst->t * inst->dtau;
+  const double log_cap = std::log(1e12);
+  std::vector<int> ns_try;
+  for (int ns : ns_list)
+    if (ns <= Lam && ns * per <= log_cap) ns_try.push_back(ns);
+  if (ns_try.empty()) ns_try.push_back(std::max(1, std::min(Lam, (int)std::floor(log_cap / std::max(per, 1e-3)))));
   const int prec = opt.precision;
   opt.precision = BSS_PREC_FP64;   // phases 1 and 2 run every slice in FP64
-  for (int ns : ns_list) {
-    if (ns > Lam) break;
+  for (int ns : ns_try) {
     Trial t;
     t.k = k_auto; t.ns = ns; t.m32 = 0;
     const bss_status st = consider(t);

@@ -85,6 +85,60 @@ def test_multigrid_grid_at_beta20():
         print(f"[gpu] L={L} dtau={dt}: k={p['delay_k']} n_stab={p['n_stab']} ok", flush=True)
 
 
+def tuned_entries():
+    from paper_1504_05090_amd import tuning
+    return [e for e in tuning.load("gfx950") if e["precision"] == "fp64"]
+
+
+@pytest.mark.parametrize("e", tuned_entries(), ids=lambda e: f"N{e['N']}-Lam{e['Lambda']}")
+def test_tuned_table_entry_against_exact_green(e):
+    """Every FP64 entry of the committed tuning table (block lengths past the
+    automatic rule's, up to a block condition of 1e12): one chain swept once
+    with the entry's delay depth and block length follows the oracle chain
+    with that block length bit for bit, and its sweep-end G equals the exact
+    G (oracle, n_stab = 1) to 1e-10."""
+    L, beta, dtau, U, t = e["L"], e["beta"], e["dtau"], e["U"], e["t"]
+    print(f"[gpu] tuned entry L={L} dtau={dtau}: k={e['delay_k']} n_stab={e['n_stab']}", flush=True)
+    g = bss.Context([dict(L=L, U=U, t=t, beta=beta, dtau=dtau, seed=BASE_SEED, n_chains=1, delay_k=e["delay_k"],
+                          n_stab=e["n_stab"])], precision="fp64")
+    p = g.params()
+    assert (p["delay_k"], p["n_stab"]) == (e["delay_k"], min(e["n_stab"], p["Lambda"]))
+    g.sweep(1)
+    o = oracle.Chain(L, U, t, beta, dtau, BASE_SEED, 0, 0, p["n_stab"])
+    o.sweep(1)
+    f = o.field()
+    assert np.array_equal(g.field(), f)
+    ex = oracle.Chain(L, U, t, beta, dtau, BASE_SEED, 0, 0, 1)
+    for s in range(2):
+        err = rel(g.green(0, 0, s), ex.fresh_green(1, s, f))
+        print(f"[gpu]   spin {s}: sweep-end rel|dG| vs exact {err:.3e}", flush=True)
+        assert err < 1e-10
+
+
+def test_batch_with_tuned_parameters_against_oracle():
+    """The multigrid grid at beta = 20 in one batch with the table's
+    per-instance delay depth and block length: one sweep of two chains per
+    instance follows the oracle chains with those block lengths (fields bit
+    for bit, sweep-end G to 1e-10)."""
+    from paper_1504_05090_amd import tuning
+    insts = tuning.apply([dict(L=L, U=2.0, t=T, beta=20.0, dtau=dt, seed=BASE_SEED, n_chains=2)
+                          for L, dt in MULTIGRID_AT_BETA20], "fp64", arch="gfx950")
+    assert sum(d["tuned"] for d in insts) >= 1
+    print("[gpu] multigrid grid at beta = 20 with tuned parameters", flush=True)
+    g = bss.Context(insts, precision="fp64")
+    g.sweep(1)
+    for j, d in enumerate(insts):
+        p = g.params(j)
+        if d["tuned"]:
+            assert (p["delay_k"], p["n_stab"]) == (d["delay_k"], min(d["n_stab"], p["Lambda"]))
+        for c in range(2):
+            o = oracle.Chain(d["L"], 2.0, T, 20.0, d["dtau"], BASE_SEED, j, c, p["n_stab"])
+            o.sweep(1)
+            assert np.array_equal(g.field(j, c), o.field()), (j, c)
+            for s in range(2):
+                assert rel(g.green(j, c, s), o.green(s)) < 1e-10, (j, c, s)
+
+
 def oracle_estimates(L, U, beta, dtau, n_stab, chains, warm, meas):
     """Per-chain means over `meas` measured sweeps (after `warm`) of D,
     G(tau_l, k) and the spin correlation C(r) (from the same fresh G at
