@@ -24,6 +24,7 @@
 //   qr_solve: M Z = B by M = Q R (no pivoting), Z = R^{-1} Q^T B
 #include "common.h"
 #include "kernels.h"
+#include "qr_order.h"
 
 namespace bss {
 
@@ -165,11 +166,10 @@ __device__ __forceinline__ int panel_factor(const Lds &s, int m, int w, int *swp
     int p = j;
     if (PIVOT) {
       const int lane = t & 63;
-      double best = (j + lane < w) ? s.pn[j + lane] : -1.0;
-      if (isnan(best)) best = -1.0;
+      double best = (j + lane < w) ? rank_key(s.pn[j + lane]) : -1.0;
       p = j + lane;
       auto take = [&](double ob, int op) {
-        if (ob > best || (ob == best && op < p)) { best = ob; p = op; }
+        if (ranks_before(ob, op, best, p)) { best = ob; p = op; }
       };
       take(dpp_dbl<DPP_XOR1>(best), dpp_int<DPP_XOR1>(p));
       take(dpp_dbl<DPP_XOR2>(best), dpp_int<DPP_XOR2>(p));
@@ -596,12 +596,9 @@ __device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int
   // and the ranks of the remaining columns are a permutation of 0..N-c0-1
   if (t == 0) s.nuout[0] = 0.0;   // no column outside the panel
   for (int q = c0 + t; q < N; q += QT) {
-    const double nq = isnan(s.norms[q]) ? -1.0 : s.norms[q];
+    const double nq = rank_key(s.norms[q]);
     int r = 0;
-    for (int p = c0; p < N; ++p) {
-      const double np_ = isnan(s.norms[p]) ? -1.0 : s.norms[p];
-      r += (np_ > nq) || (np_ == nq && p < q);
-    }
+    for (int p = c0; p < N; ++p) r += ranks_before(rank_key(s.norms[p]), p, nq, q);
     rank[q] = r;
   }
   __syncthreads();
