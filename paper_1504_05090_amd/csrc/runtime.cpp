@@ -240,15 +240,20 @@ int auto_fp32_slices(double lambda, int n_stab) {
   return std::max(0, std::min(s, n_stab));
 }
 
-// Shards per instance.  A context of one instance splits its chains into up
-// to four shards of at least 32 chains, each on its own streams: the flip
-// kernel of a shard fills only as many CUs as it has chains and the QRs are
-// latency-bound, so the shards' launches overlap (the 16 x 16, 128-chain
-// sweep: 83.1 ms with one shard, 80.9 with two, 79.9 with four).  A batch of
-// several instances already overlaps its instances and keeps one shard each.
-// The environment variable BSS_SHARDS = 1..8 overrides, for tuning.
-int shard_count(int C, int n_instances) {
-  int s = n_instances == 1 ? std::min(4, C / 32) : 1;
+// Shards per instance.  A context of one instance whose sweeps are replayed
+// from captured graphs splits its chains into up to four shards of at least
+// 32 chains, each on its own streams: the flip kernel of a shard fills only
+// as many CUs as it has chains and the QRs are latency-bound, so the shards'
+// launches overlap (16 x 16, 128 chains, FP64: 73.9 ms per sweep with one
+// shard, 72.3 with two, 71.6 with four).  A context that launches directly
+// (the FP32 drift controller, BSS_FLAG_NO_GRAPH, BSS_FLAG_PROFILE) keeps one
+// shard: with four, its eight streams share the process's four hardware
+// queues, and the sweep took 78 to 104 ms from run to run, against 73 ms with
+// one (mixed, the same workload).  A batch of several instances already
+// overlaps its instances and keeps one shard each.  The environment variable
+// BSS_SHARDS = 1..8 overrides, for tuning.
+int shard_count(int C, int n_instances, bool direct) {
+  int s = n_instances == 1 ? std::min(direct ? 1 : 4, C / 32) : 1;
   if (const char *env = std::getenv("BSS_SHARDS")) {
     const int v = std::atoi(env);
     if (v >= 1 && v <= 8) s = v;
@@ -336,7 +341,8 @@ bool resolve(const bss_instance *in, int n, const bss_options &opt, std::vector<
     UInst U;
     U.first = (int)out.size();
     U.C = I.Ctot; U.N = I.N; U.Lam = I.Lam;
-    U.count = shard_count(I.Ctot, n);
+    const bool direct = I.adapt || (opt.flags & (BSS_FLAG_NO_GRAPH | BSS_FLAG_PROFILE)) != 0;
+    U.count = shard_count(I.Ctot, n, direct);
     int c0 = 0;
     for (int s = 0; s < U.count; ++s) {
       Shard J = I;
