@@ -40,20 +40,21 @@ METRIC = "HS field updates/sec at 16x16, β=20 (FP32+FP64-stab vs FP64), max|ΔG
 PEAK = {"f32": 157.3e12, "f64": 78.6e12}
 HBM_PEAK = 8.0e12
 
-# HBM bytes per launch of one 32-chain shard (64 matrices), FETCH_SIZE x f +
-# WRITE_SIZE x w with the scales f, w a device copy of known size gives
-# (profiles/*_hbm_traffic.md), valid while the kernel's source file is the
-# one the counters were taken on (sha1 prefix); otherwise null.
+# HBM bytes per launch in the timed configuration (one 128-chain shard, 256
+# matrices), FETCH_SIZE x f + WRITE_SIZE x w with the scales f, w a device
+# copy of known size gives (profiles/*_hbm_traffic.md), valid while the
+# kernel's source file is the one the counters were taken on (sha1 prefix);
+# otherwise null.
 TRAFFIC = {
     "dense": {
-        "qr_udv": (5.350e8, "k_qr.hip", "7f1ff4059918"),
-        "qr_solve": (5.208e8, "k_qr.hip", "7f1ff4059918"),
-        "flip_f64": (1.531e8, "k_flip.hip", "f441bb0b7329"),
-        "flip_f32": (4.01e7, "k_flip.hip", "f441bb0b7329"),
+        "qr_udv": (3.9507e9, "k_qr.hip", "489fc1e42855"),
+        "qr_solve": (2.9530e9, "k_qr.hip", "489fc1e42855"),
+        "flip_f64": (1.0869e9, "k_flip.hip", "f441bb0b7329"),
+        "flip_f32": (4.829e8, "k_flip.hip", "f441bb0b7329"),
         # the FP64 NN GEMM kernel (wraps, block products and UDV products share it)
-        "wrap_f64": (1.141e8, "k_gemm.hip", "57c2c9444073"),
-        "gemm_f64": (1.141e8, "k_gemm.hip", "57c2c9444073"),
-        "wrap_f32": (4.41e7, "k_gemm.hip", "57c2c9444073"),
+        "wrap_f64": (4.525e8, "k_gemm.hip", "57c2c9444073"),
+        "gemm_f64": (4.525e8, "k_gemm.hip", "57c2c9444073"),
+        "wrap_f32": (1.703e8, "k_gemm.hip", "57c2c9444073"),
     },
     "kronecker": {},
 }
@@ -398,7 +399,9 @@ def main():
     scale = 1e9 if bound == "hbm" else 1e12
     roofline = {"kernel": dom, "bound": bound, "achieved": achieved / scale if achieved else None,
                 "peak": peak / scale if peak else None, "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
-                "frac": (achieved / peak) if (achieved and peak) else None, "traffic": traffic_of(dom, args.hopping),
+                "frac": (achieved / peak) if (achieved and peak) else None,
+                # the counters were taken on 256-matrix launches
+                "traffic": traffic_of(dom, args.hopping) if mats == 256 else None,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "algorithmic_per_launch": amount, "avg_launch_ms": avg_ms, "launches": launches,
                 "shards": shards, "matrices_per_launch": mats, "fp32_slices": m32,
