@@ -223,6 +223,90 @@ def run_batch(bss, insts, steps, warmup, flags):
     return upd * steps / (ms / 1e3), ms / steps, graph, params
 
 
+def post_processing(bss, ctx, p):
+    """The library's analysis on the timed chains' own measurements (paper
+    Sec. 3 and 4): G(tau_l, k) at k = (pi, 0) with its standard errors ->
+    maximum-entropy spectrum at the historic alpha (eq. (4)) -> smooth G(tau)
+    -> Matsubara transform (eq. (5)) -> Dyson self-energy (eq. (6), eps_k = 0,
+    mu = 0: Re Sigma vanishes by particle-hole symmetry); C(r) -> xi.  Host
+    code; each step timed.  Returns (summary, inputs for the oracle's turn)."""
+    L, beta, dtau = p["L"], p["beta"], p["dtau"]
+    lam = int(round(beta / dtau))
+    gm, ge = ctx.gtau_k()
+    kpi0 = L // 2                                    # k = (pi, 0): mx = L/2, my = 0
+    tau = np.arange(lam + 1) * dtau
+    G, sig = gm[:, kpi0].copy(), np.maximum(ge[:, kpi0], 1e-6)
+    w = np.linspace(-4.0, 4.0, 161)
+    m = np.full_like(w, 1.0 / 8.0)
+    tau_f = np.linspace(0.0, beta, 401)
+    out, t = {"k": "(pi, 0)", "tau_points": lam + 1, "omega_points": len(w), "matsubara_frequencies": 32}, {}
+    inputs = dict(tau=tau, G=G, sig=sig, w=w, m=m, beta=beta, tau_f=tau_f, L=L)
+    try:
+        t0 = time.perf_counter()
+        A, alpha, chi2 = bss.mem_spectrum(tau, G, sig, beta, w, m)
+        t["mem_spectrum"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Gs = bss.mem_green(beta, w, A, tau_f)
+        t["mem_green"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        giw = bss.matsubara(tau_f, Gs, beta, 32)
+        t["matsubara"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sigma = bss.dyson(beta, 0.0, 0.0, giw)
+        t["dyson"] = time.perf_counter() - t0
+        out.update(alpha=alpha, chi2=chi2, spectral_weight=float(np.trapezoid(A, w)),
+                   sum_rule_G0_plus_Gbeta=float(Gs[0] + Gs[-1]),
+                   im_sigma_iw0=float(sigma[0].imag), max_abs_re_sigma=float(np.max(np.abs(sigma.real))),
+                   max_abs_im_sigma=float(np.max(np.abs(sigma.imag))))
+        inputs.update(A=A, alpha=alpha, Gs=Gs, giw=giw, sigma=sigma)
+    except Exception as e:   # e.g. no historic alpha for these data
+        out["mem_error"] = str(e)
+    cm, _ = ctx.spin_corr()
+    out.update(spin_corr_C0=float(cm[0]), spin_corr_C1=float(cm[1]))
+    inputs["C"] = cm
+    try:
+        t0 = time.perf_counter()
+        xi, _ = bss.correlation_length(L, cm)
+        t["correlation_length"] = time.perf_counter() - t0
+        out["xi"] = xi
+    except Exception as e:   # no decay over the half lattice
+        out["xi_error"] = str(e)
+    out["library_ms"] = {k2: v * 1e3 for k2, v in t.items()}
+    return out, inputs
+
+
+def post_processing_oracle(post, inp):
+    """The oracle's versions of the same steps on the same inputs, timed on the
+    host, and their largest differences from the library's results."""
+    from oracle import analysis as an
+    from oracle import mem
+    t = {}
+    if "A" in inp:
+        t0 = time.perf_counter()
+        Ao, ao, _ = mem.spectrum(inp["tau"], inp["G"], inp["sig"], inp["beta"], inp["w"], inp["m"])
+        t["mem_spectrum"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Gso = mem.green(inp["tau_f"], inp["w"], Ao, inp["beta"])
+        t["mem_green"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        giwo = an.matsubara(inp["tau_f"], Gso, inp["beta"], 32)
+        t["matsubara"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sigo = an.dyson(an.matsubara_frequencies(inp["beta"], 32), 0.0, 0.0, giwo)
+        t["dyson"] = time.perf_counter() - t0
+        big = Ao > 1e-6 * Ao.max()
+        post["vs_oracle"] = {"alpha_rel": abs(inp["alpha"] - ao) / ao,
+                             "A_rel_max": float(np.max(np.abs(inp["A"] - Ao)[big] / Ao[big])),
+                             "G_smooth_abs_max": float(np.max(np.abs(inp["Gs"] - Gso))),
+                             "sigma_abs_max": float(np.max(np.abs(inp["sigma"] - sigo)))}
+    if "xi" in post:
+        t0 = time.perf_counter()
+        xio, _ = an.correlation_length(inp["C"], inp["L"])
+        t["correlation_length"] = time.perf_counter() - t0
+        post.setdefault("vs_oracle", {})["xi_rel"] = abs(post["xi"] - xio) / abs(xio)
+    post["oracle_ms"] = {k2: v * 1e3 for k2, v in t.items()}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -336,6 +420,8 @@ def main():
     ms_meas = timed_sweeps(ctx, stream, n_meas, measure=True)
     value_meas = updates_per_step * n_meas / (ms_meas / 1e3)
     print(f"[bench] mixed with measurement: {ms_meas / n_meas:.2f} ms/step", file=sys.stderr, flush=True)
+    post, post_in = post_processing(bss, ctx, p)
+    print(f"[bench] post-processing of the measured G(tau, k) and C(r): {post}", file=sys.stderr, flush=True)
     ckpt = ctx.save()
     field0 = ctx.field(0, 0)
 
@@ -441,6 +527,7 @@ def main():
     cpu, d_exact, d_same = None, None, None
     if not args.no_cpu_baseline:
         cpu, d_exact, d_same = cpu_baseline_leg(p, n_stab, ctx, C)
+        post_processing_oracle(post, post_in)
         print(f"[bench] cpu oracle: {cpu}; sampled sweep-end max rel|dG|: vs exact {d_exact:.3e}, vs oracle at "
               f"n_stab={n_stab} {d_same:.3e}", file=sys.stderr, flush=True)
     del ctx
@@ -465,7 +552,7 @@ def main():
         "value_with_measurement": value_meas, "ms_per_step_with_measurement": ms_meas / n_meas,
         "fp64_path": fp64, "speedup_vs_fp64": (value / fp64_value) if fp64_value else None,
         "all_fp32_bulk": all32, "kronecker_hopping": kron, "rank1_path": rank1, "multigrid_batch": batch,
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "post_processing": post,
     }
     print(json.dumps(out))
 
