@@ -8,7 +8,8 @@
 //     m_i = <n_i,up> - <n_i,dn> = G_dn,ii - G_up,ii
 //   G(tau_l, k) = -1/2 sum_sigma (1/N) sum_ij cos(k.(r_i - r_j)) G_sigma,ij(tau_l, 0)
 // The second is evaluated through the lattice-averaged g(delta) =
-// (1/N) sum_i G_{i+delta, i}, then G(tau_l, k) = -1/2 sum_sigma sum_delta cos(k.delta) g(delta).
+// (1/N) sum_i G_{i+delta, i}, then G(tau_l, k) = -1/2 sum_delta cos(k.delta) g(delta)
+// with g summed over both spins.
 #include "common.h"
 #include "kernels.h"
 #include "measure.h"
@@ -73,34 +74,59 @@ __global__ __launch_bounds__(256) void k_meas_docc(MeasState ms, const double *G
   if (threadIdx.x == 0) ms.docc[(long)c * ms.nbins + ms.cur[c]] += s / N;
 }
 
-// One chain per block: g_sigma(delta) summed over spins, then the cosine
-// transform, added to the slice-l row of the chain's current bin.
+// One chain per block: g(delta) summed over spins, then its cosine transform,
+// added to the slice-l row of the chain's current bin.
+//  - g(delta) = (1/N) sum_r G_{r, r - delta}: each thread owns displacements
+//    delta and walks the rows r, so at each step the lanes of a wavefront
+//    read within one row of G (the lattice difference r - delta permutes the
+//    columns);
+//  - the transform is separable, sum_delta cos(k.delta) g(delta) =
+//    Re sum_dy e^{i ky dy} sum_dx e^{i kx dx} g(dx, dy), taken as two passes of
+//    L terms with cos and sin of 2 pi m / L from a table.
 __global__ __launch_bounds__(256) void k_meas_gk(MeasState ms, const double *Gt, int L, int l) {
-  extern __shared__ double gd[];   // [N] g(delta) summed over spins
+  extern __shared__ double sh[];
   const int N = L * L, c = blockIdx.x;
+  double *gd = sh, *hre = sh + N, *him = sh + 2 * N, *cs = sh + 3 * N, *sn = cs + L;
   const double *g0 = Gt + (2L * c) * N * N, *g1 = g0 + (long)N * N;
+  for (int m = threadIdx.x; m < L; m += blockDim.x) {
+    cs[m] = cospi(2.0 * m / L);
+    sn[m] = sinpi(2.0 * m / L);
+  }
   for (int dlt = threadIdx.x; dlt < N; dlt += blockDim.x) {
     const int dx = dlt % L, dy = dlt / L;
     double s = 0.0;
-    for (int i = 0; i < N; ++i) {
-      const int xi = i % L, yi = i / L;
-      const int r = ((xi + dx) % L) + L * ((yi + dy) % L);
-      s += g0[(long)r * N + i] + g1[(long)r * N + i];
+    for (int r = 0; r < N; ++r) {
+      const int col = ((r % L) - dx + L) % L + L * (((r / L) - dy + L) % L);
+      s += g0[(long)r * N + col] + g1[(long)r * N + col];
     }
     gd[dlt] = s / N;
+  }
+  __syncthreads();
+  // h(mx, dy) = sum_dx e^{2 pi i mx dx / L} g(dx, dy)
+  for (int e = threadIdx.x; e < N; e += blockDim.x) {
+    const int mx = e % L, dy = e / L;
+    double re = 0.0, im = 0.0;
+    for (int dx = 0; dx < L; ++dx) {
+      const int ph = (mx * dx) % L;
+      re += cs[ph] * gd[dx + L * dy];
+      im += sn[ph] * gd[dx + L * dy];
+    }
+    hre[e] = re;
+    him[e] = im;
   }
   __syncthreads();
   double *out = ms.gk + ((long)c * ms.nbins_g + (ms.nbins_g == 1 ? 0 : ms.cur[c])) * ms.glen + (long)l * N;
   for (int k = threadIdx.x; k < N; k += blockDim.x) {
     const int mx = k % L, my = k / L;
     double s = 0.0;
-    for (int dlt = 0; dlt < N; ++dlt) {
-      const int ph = (mx * (dlt % L) + my * (dlt / L)) % L;
-      s += cospi(2.0 * ph / L) * gd[dlt];
+    for (int dy = 0; dy < L; ++dy) {
+      const int ph = (my * dy) % L;
+      s += cs[ph] * hre[mx + L * dy] - sn[ph] * him[mx + L * dy];
     }
     out[k] += -0.5 * s;
   }
 }
+
 // One chain per block: the local moments in LDS, then one displacement r
 // per thread summed over the sites i (j = i + r with periodic wrap).
 __global__ __launch_bounds__(256) void k_meas_sc(MeasState ms, const double *Gf, int L) {
@@ -140,7 +166,7 @@ hipError_t meas_sc(const MeasState &ms, const double *Gf, int chains, int L, hip
   return hipGetLastError();
 }
 hipError_t meas_gk(const MeasState &ms, const double *Gt, int chains, int L, int l, hipStream_t s) {
-  hipLaunchKernelGGL(k_meas_gk, dim3(chains), dim3(256), sizeof(double) * L * L, s, ms, Gt, L, l);
+  hipLaunchKernelGGL(k_meas_gk, dim3(chains), dim3(256), sizeof(double) * (3 * L * L + 2 * L), s, ms, Gt, L, l);
   return hipGetLastError();
 }
 
