@@ -2,6 +2,7 @@
 declared in include/bssqmc.h, and rejects invalid arguments before touching a
 device."""
 import ctypes
+import math
 import os
 import re
 
@@ -77,6 +78,31 @@ def test_workspace_size_is_host_only():
     one = ctypes.c_size_t()
     assert bss.lib().bss_workspace_size(inst, 1, ctypes.byref(o), ctypes.byref(one)) == bss.BSS_OK
     assert n.value > one.value > 0
+
+
+def _workspace(inst, **opt):
+    n = ctypes.c_size_t()
+    o = bss.make_options(**opt)
+    assert bss.lib().bss_workspace_size(ctypes.byref(inst), 1, ctypes.byref(o), ctypes.byref(n)) == bss.BSS_OK
+    return n.value
+
+
+def test_automatic_block_length_follows_the_hopping():
+    """The automatic n_stab keeps the block product's condition near 1e8 with
+    log cond(B) = 2 lambda + 8 t dtau per slice: at U = 2, dtau = 0.5 that is
+    n_stab = 5 for t = 0.25 and 4 for t = 0.5.  The workspace (host-only) grows
+    with the number of blocks, so the automatic choice must size it exactly as
+    the explicit block length does."""
+    for t, ns in ((0.25, 5), (0.5, 4)):
+        lam = math.acosh(math.exp(0.5 * 0.5 * 2.0))
+        assert int(math.log(1e8) / (2 * lam + 8 * t * 0.5)) == ns
+        inst = bss.Instance(8, 2.0, t, 20.0, 0.5, 1, 4)
+        assert _workspace(inst) == _workspace(inst, n_stab=ns), t
+        assert _workspace(inst) != _workspace(inst, n_stab=ns + 1), t
+    # a per-instance block length overrides the options' and the automatic one
+    inst = bss.Instance(8, 2.0, 0.25, 20.0, 0.5, 1, 4, 0, 8)
+    assert _workspace(inst) == _workspace(bss.Instance(8, 2.0, 0.25, 20.0, 0.5, 1, 4), n_stab=8)
+    assert _workspace(inst, n_stab=3) == _workspace(inst)
 
 
 def test_null_safe_calls():
