@@ -210,24 +210,43 @@ bss_status bss_create_batch(const bss_instance *inst, int32_t n_inst, const bss_
 bss_status bss_workspace_size(const bss_instance *inst, int32_t n_inst, const bss_options *opt,
                               size_t *bytes);
 
-/* Run n_sweeps full sweeps of every chain of every instance (asynchronous).
- * measure != 0: after each sweep accumulate double occupancy, the spin
- * correlation and G(tau_l, k) from the fresh G(tau = 0).  STATE if an instance is not at slice 1. */
+/* Run n_sweeps full sweeps of every chain of every instance (asynchronous, on
+ * the context's stream).  A sweep is the Monte Carlo step over the Ising field
+ * of eq. (3) (paper Sec. 2): for l = 1..Lambda and i = 0..N-1, the proposal
+ * h_{l,i} -> -h_{l,i} is accepted iff u < R_up R_dn with R_sigma =
+ * 1 + (1 - G_sigma,ii) Delta_sigma; accepted flips update G by delayed
+ * Sherman-Morrison; after each slice G <- B_l G B_l^{-1}; after every n_stab
+ * slices and at l = Lambda, G is recomputed in FP64 from the UDV-stabilised
+ * B chain (G_sigma = M_sigma^{-1}, eq. (3)).  measure != 0: after each sweep
+ * accumulate double occupancy, the spin correlation and G(tau_l, k) from the
+ * fresh G(tau = 0).  STATE if an instance is not at slice 1.  Failures found
+ * on the device (a non-finite or non-positive ratio, a non-finite G, a drift
+ * above drift_abort) poison the context; this call or a later one returns
+ * NUMERICAL. */
 bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure);
 
-/* Advance every instance by n_slices slices (asynchronous); sweeps may end
- * part-way.  Intended for slice-by-slice checks; no measurement. */
+/* Advance every instance by n_slices slices of the sweep of bss_sweep
+ * (asynchronous); sweeps may end part-way.  Intended for slice-by-slice
+ * checks; no measurement; the same failure behaviour. */
 bss_status bss_step_slices(bss_ctx *c, int32_t n_slices);
 
-/* Mean (and standard error, if stderr_out != NULL) of G(tau_l, k), paper sign,
- * over all measured sweeps of instance `inst`: out[l * N + k], l = 0..Lambda.
- * len must equal (Lambda + 1) * N.  The error is over chains (per-chain means)
- * when there are >= 2 chains, else over 16..31 equal bins of one chain.
- * STATE if nothing was measured. */
+/* Mean (and standard error, if stderr_out != NULL) of G(tau_l, k), the
+ * output the paper's Sec. 2 names (G_ij(tau_l) on the slice grid) with the
+ * sign of eq. (4): G(tau_l, k) = -1/2 sum_sigma (1/N) sum_ij
+ * cos(k.(r_i - r_j)) <c_i(tau_l) c_j^+(0)>, k = 2 pi (mx, my) / L with
+ * index k = mx + L my, over all measured sweeps of instance `inst`:
+ * mean[l * N + k], l = 0..Lambda (host arrays of len doubles; stderr_out may
+ * be NULL).  G(tau_l, 0) is the stable time-displaced Green function: exact
+ * products of B from the recomputed G at block boundaries.  len must equal
+ * (Lambda + 1) * N.  The error is over chains (per-chain means) when there
+ * are >= 2 chains, else over 16..31 equal bins of one chain.  STATE if nothing
+ * was measured; NUMERICAL if the context is poisoned. */
 bss_status bss_measure_gtau_k(bss_ctx *c, int32_t inst, double *mean, double *stderr_out,
                               int64_t len);
 
-/* Mean (and standard error) of D = (1/N) sum_i <n_i,up n_i,dn>. */
+/* Mean (and standard error; stderr_out may be NULL) of the double occupancy
+ * D = (1/N) sum_i <n_i,up n_i,dn> = (1/N) sum_i (1 - G_up,ii)(1 - G_dn,ii)
+ * (Wick's theorem for each field), errors as for bss_measure_gtau_k. */
 bss_status bss_measure_double_occ(bss_ctx *c, int32_t inst, double *mean, double *stderr_out);
 
 /* Real-space spin correlation of Sec. 4 (Fig. 5), accumulated with the other
