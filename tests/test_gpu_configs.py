@@ -12,6 +12,8 @@
   estimators formed from the oracle's per-sweep measurements of the same
   chains.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -313,3 +315,39 @@ def test_observables_at_u2_within_error_bars_of_the_exact_2x2_values():
     print(f"[gpu] D = {d:.6f} +- {de:.1e} (exact {d_ex:.6f}, z = {zd:.2f}); G(tau, k) max z = {zg:.2f}; "
           f"C(r) max z = {zc:.2f} (C(0) = {cm[0]:.5f}, exact {c_ex[0]:.5f})", flush=True)
     assert zd < 4.0 and zc < 4.0 and zg < 4.5
+
+
+def test_rank1_4x4_workload_against_independent_oracle_chains():
+    """The 4 x 4 rank-1 workload (U = 2, beta = 4, dtau = 0.5, k = 1, n_stab = 4)
+    on the GPU, one chain of 200 + 1000 sweeps (errors from its bins), against
+    four independent oracle chains (another Philox key; 200 + 250 sweeps each,
+    errors over the chains): D within 3.5 combined standard errors, the 144
+    values of G(tau_l, k) within 5."""
+    L, U, beta, dtau, ns = 4, 2.0, 4.0, 0.5, 4
+    print("[gpu] 4x4 rank-1, 1 chain x (200 + 1000) sweeps against 4 independent oracle chains", flush=True)
+    g = bss.Context([dict(L=L, U=U, t=T, beta=beta, dtau=dtau, seed=BASE_SEED, n_chains=1)], precision="fp64",
+                    delay_k=1, n_stab=ns)
+    g.sweep(200)
+    g.sweep(1000, measure=True)
+    d, de = g.double_occ()
+    gm, ge = g.gtau_k()
+    dd, gg = [], []
+    for c in range(4):
+        o = oracle.Chain(L, U, T, beta, dtau, BASE_SEED + 7919, 1, c, ns)
+        o.sweep(200)
+        ds, gs = [], []
+        for _ in range(250):
+            o.sweep(1)
+            x, gk = o.measure()
+            ds.append(x)
+            gs.append(gk)
+        dd.append(np.mean(ds))
+        gg.append(np.mean(gs, axis=0))
+    dd, gg = np.array(dd), np.array(gg)
+    od, ode = dd.mean(), dd.std(ddof=1) / 2.0
+    og, oge = gg.mean(axis=0), gg.std(axis=0, ddof=1) / 2.0
+    zd = abs(d - od) / math.hypot(de, ode)
+    zg = np.max(np.abs(gm - og) / np.maximum(np.hypot(ge, oge), 1e-12))
+    print(f"[gpu] D: GPU {d:.5f} +- {de:.1e}, oracle {od:.5f} +- {ode:.1e} (z = {zd:.2f}); G(tau, k) max z = {zg:.2f}",
+          flush=True)
+    assert zd < 3.5 and zg < 5.0
