@@ -10,7 +10,10 @@ FP32 G, flips, flushes and wraps in the last slices of every block, as many
 as the library's drift controller allows (an FP32 error made s wraps before a
 recomputation grows ~e^{2 lambda} per wrap; the controller starts in FP64 and
 keeps the measured relative drift below 1e-3), FP64 everywhere else and for
-all stabilisation.  The all-FP64 path is timed beside it.
+all stabilisation.  The controller adapts the count during the warm-up sweeps
+and then holds it, so the timed sweeps are replayed from one captured sweep
+graph; the same path with the controller adapting after every timed sweep
+(direct launches) and the all-FP64 path are timed beside it.
 
 Prints one JSON line: updates/s of the headline path (everything resident on
 the GPU, chains equilibrated by the warm-up sweeps) and of the FP64 path, the
@@ -100,11 +103,12 @@ def timed_sweeps(ctx, stream, n, measure=False):
     return e0.elapsed_time(e1)
 
 
-def run_path(bss, inst, precision, k, n_stab, steps, warmup, fp32_slices=0, flags=0, drift_abort=None):
+def run_path(bss, inst, precision, k, n_stab, steps, warmup, fp32_slices=0, flags=0, drift_abort=None,
+             adapt_sweeps=0):
     import torch
     stream = torch.cuda.Stream()
     ctx = bss.Context([inst], precision=precision, delay_k=k, n_stab=n_stab, flags=flags, stream=stream,
-                      fp32_slices=fp32_slices, drift_abort=drift_abort)
+                      fp32_slices=fp32_slices, drift_abort=drift_abort, fp32_adapt_sweeps=adapt_sweeps)
     ctx.sweep(warmup)
     ctx.synchronize()
     ctx.reset_stats()
@@ -116,7 +120,7 @@ def summary(st):
     return {"acceptance": st["accepted"] / max(1, st["proposals"]), "drift_rel_max": st["drift_rel_max"],
             "drift_rel_mean": st["drift_rel_mean"], "fp32_slices": st["fp32_slices"],
             "fp32_fraction": st["fp32_fraction"], "fp32_rejected": st["fp32_rejected"],
-            "fp32_fused": st["fp32_fused"]}
+            "fp32_fused": st["fp32_fused"], "fp32_settled": st["fp32_settled"], "sweep_graph": st["sweep_graph"]}
 
 
 def fp32_error_on_identical_history(bss, inst, field, k, n_stab, m32, n_slices):
@@ -160,9 +164,9 @@ def fp32_error_on_identical_history(bss, inst, field, k, n_stab, m32, n_slices):
 
 def profile_pass(bss, inst, k, n_stab, m32, ckpt, steps, flags):
     """Per-launch HIP-event timings of every kernel family in the timed
-    configuration (same shards, the FP32 slice count the controller ended
-    on), from the timed context's checkpoint: direct launches with an event
-    pair around each launch on the stream it is issued on."""
+    configuration (same shards, the FP32 slice count the controller held),
+    from the timed context's checkpoint: direct launches with an event pair
+    around each launch on the stream it is issued on."""
     import torch
     stream = torch.cuda.Stream()
     prec = "mixed" if m32 > 0 else "fp64"
@@ -408,8 +412,12 @@ def main():
     kron_head = args.hopping == "kronecker"
     hflags = bss.FLAG_KRONECKER_HOPPING if kron_head else 0
 
-    # 1. the headline: mixed precision, automatic FP32 slice count
-    ctx, stream, ms, st = run_path(bss, inst, "mixed", k, n_stab, args.steps, args.warmup, flags=hflags)
+    # 1. the headline: mixed precision, automatic FP32 slice count, adapted
+    # during all but the last two warm-up sweeps and then held (the first held
+    # sweep is captured, still inside the warm-up)
+    settle = max(1, args.warmup - 2)
+    ctx, stream, ms, st = run_path(bss, inst, "mixed", k, n_stab, args.steps, args.warmup, flags=hflags,
+                                   adapt_sweeps=settle)
     value = updates_per_step * args.steps / (ms / 1e3)
     mixed = summary(st)
     m32 = mixed["fp32_slices"]
@@ -432,7 +440,15 @@ def main():
     print(f"[bench] FP32 slices ({m32_err} per block) vs FP64 path on one history: max rel|dG| {fp32_err:.3e}, "
           f"FP64 slices identical: {fp64_slices_identical}", file=sys.stderr, flush=True)
 
-    # 3. the FP64 path
+    # 3. the same path with the controller adapting after every sweep, timed
+    # sweeps included (launched directly, one sweep at a time)
+    ctxe, _, mse, ste = run_path(bss, inst, "mixed", k, n_stab, args.steps, args.warmup, flags=hflags)
+    every = dict(summary(ste), value=updates_per_step * args.steps / (mse / 1e3), ms_per_step=mse / args.steps)
+    del ctxe
+    print(f"[bench] mixed, controller adapting after every sweep: {mse / args.steps:.2f} ms/step", file=sys.stderr,
+          flush=True)
+
+    # 4. the FP64 path
     fp64, fp64_value = None, None
     if not args.no_fp64:
         ctx64, _, ms64, st64 = run_path(bss, inst, "fp64", k, n_stab, args.steps, args.warmup, flags=hflags)
@@ -450,17 +466,17 @@ def main():
         print(f"[bench] all slices FP32 (not valid at this coupling): {all32}", file=sys.stderr, flush=True)
         del ctx32
 
-    # 4. the Kronecker-factor option of e^{-+dtau K} on the same workload
+    # 5. the Kronecker-factor option of e^{-+dtau K} on the same workload
     kron = None
     if not args.no_kronecker and not kron_head:
         ctxk, _, msk, stk = run_path(bss, inst, "mixed", k, n_stab, args.steps, args.warmup,
-                                     flags=bss.FLAG_KRONECKER_HOPPING)
+                                     flags=bss.FLAG_KRONECKER_HOPPING, adapt_sweeps=settle)
         kval = updates_per_step * args.steps / (msk / 1e3)
         kron = dict(summary(stk), value=kval, ms_per_step=msk / args.steps, speedup_vs_headline=kval / value)
         del ctxk
         print(f"[bench] Kronecker hopping: {kron}", file=sys.stderr, flush=True)
 
-    # 5. roofline of the dominant kernel family in the timed configuration
+    # 6. roofline of the dominant kernel family in the timed configuration
     psteps = max(2, args.steps // 2)
     msp, stp, prof = profile_pass(bss, inst, k, n_stab, m32, ckpt, psteps, hflags)
     acc = stp["accepted"] / max(1, stp["proposals"])
@@ -496,12 +512,12 @@ def main():
     print(f"[bench] profile pass ({msp / psteps:.2f} ms/step): dominant {dom}, {families}", file=sys.stderr,
           flush=True)
 
-    # 6. the forced rank-1 path: HBM rate of the flip kernel
+    # 7. the forced rank-1 path: HBM rate of the flip kernel
     rank1 = None if args.no_rank1 else rank1_pass(bss, inst, 2)
     if rank1:
         print(f"[bench] rank-1 path: {rank1}", file=sys.stderr, flush=True)
 
-    # 7. the multigrid batch: 16 uneven instances x 32 chains
+    # 8. the multigrid batch: 16 uneven instances x 32 chains
     batch = None
     if not args.no_batch:
         c3 = CONFIGS["C3"]
@@ -523,7 +539,7 @@ def main():
                  "instances": params}
         print(f"[bench] batch: {batch}", file=sys.stderr, flush=True)
 
-    # 8. the cpu_baseline leg: the oracle on the host, and the sampled check
+    # 9. the cpu_baseline leg: the oracle on the host, and the sampled check
     cpu, d_exact, d_same = None, None, None
     if not args.no_cpu_baseline:
         cpu, d_exact, d_same = cpu_baseline_leg(p, n_stab, ctx, C)
@@ -538,11 +554,13 @@ def main():
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic (Markov chains from seeded Philox fields)",
         "config": {"workload": f"16x16 Hubbard BSS-QMC sweep, t=0.25, U=2, beta=20, dtau=0.5 (Lambda=40), "
                                f"{C} chains, k={k}, n_stab={n_stab}, FP32 in the last slices of each block as the "
-                               f"drift controller allows (target 1e-3), "
+                               f"drift controller allows (target 1e-3; adapted during the first {settle} warm-up "
+                               f"sweeps, then held: captured sweep graph), "
                                + ("e^{-+dtau K} through its Kronecker factors" if kron_head
                                   else "wraps and block products as dense MFMA GEMMs"),
                    "L": p["L"], "chains": C, "beta": p["beta"], "dtau": p["dtau"], "U": p["U"], "k": k,
-                   "n_stab": n_stab, "fp32_slices_final": m32, "hopping": args.hopping, "shards": st["shards"]},
+                   "n_stab": n_stab, "fp32_slices_final": m32, "hopping": args.hopping, "shards": st["shards"],
+                   "fp32_adapt_sweeps": settle, "sweep_graph": st["sweep_graph"]},
         "drift_rel_max": mixed["drift_rel_max"], "drift_rel_mean": mixed["drift_rel_mean"],
         "fp32_drift_bound": 1e-3, "fp32_fraction": mixed["fp32_fraction"], "acceptance": mixed["acceptance"],
         "fp32_rejected_ratios": mixed["fp32_rejected"], "fp32_fused": mixed["fp32_fused"],
@@ -550,7 +568,8 @@ def main():
         "fp64_slices_bit_identical": fp64_slices_identical,
         "max_dG_vs_oracle_sweep_end": d_exact, "max_dG_vs_oracle_same_n_stab": d_same,
         "value_with_measurement": value_meas, "ms_per_step_with_measurement": ms_meas / n_meas,
-        "fp64_path": fp64, "speedup_vs_fp64": (value / fp64_value) if fp64_value else None,
+        "controller_every_sweep": every, "fp64_path": fp64,
+        "speedup_vs_fp64": (value / fp64_value) if fp64_value else None,
         "all_fp32_bulk": all32, "kronecker_hopping": kron, "rank1_path": rank1, "multigrid_batch": batch,
         "roofline": roofline, "cpu_baseline": cpu, "post_processing": post,
     }

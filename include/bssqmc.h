@@ -123,9 +123,10 @@ typedef struct {
                             FP32 slice multiplies the FP32 part of the drift by
                             about e^{2 lambda}), never above the largest s with
                             2^-24 e^{2 lambda s} <= 1e-5 (may be 0 at strong
-                            coupling).  bss_sweep then waits for each sweep's
-                            recomputations before issuing the next, and launches
-                            its kernels directly (no captured sweep).  In these
+                            coupling).  While the controller adapts, bss_sweep
+                            waits for each sweep's recomputations before issuing
+                            the next, and launches its kernels directly (no
+                            captured sweep); see fp32_adapt_sweeps.  In these
                             FP32 slices a finite ratio R <= 0 (FP32 rounding of
                             a G whose entries reach 1e2..1e3) is rejected and
                             counted (bss_stats.fp32_rejected) instead of being a
@@ -135,6 +136,17 @@ typedef struct {
                             such a ratio stays a failure.  Ignored in FP64 mode. */
   double fp32_drift_target; /* the controller's bound on the relative drift;
                             0 = 1e-3                                              */
+  int32_t fp32_adapt_sweeps; /* automatic count only: 0 = the controller adapts
+                            after every sweep for the context's lifetime; n > 0 =
+                            it adapts after each of the context's first n sweeps
+                            and then holds the count it reached (bss_stats.
+                            fp32_settled).  Sweeps after that are captured and
+                            replayed like those of a fixed count.  The FP32 guard
+                            stays on: a finite ratio <= 0 in an FP32 slice is
+                            still rejected and counted, and at the start of the
+                            next bss_sweep call the instance switches to FP64
+                            (bss_stats.fp32_fused) and the context stops
+                            capturing (its sweeps launch directly from then on). */
 } bss_options;
 
 /* One (L, U, t, beta, dtau) instance with its chains.  delay_k and n_stab,
@@ -173,6 +185,8 @@ typedef struct {
                             last bss_reset_stats that ran in FP32               */
   int64_t fp32_rejected; /* ratios <= 0 rejected in the controller's FP32 slices */
   int32_t fp32_fused;    /* 1 once such a ratio switched the instance to FP64   */
+  int32_t fp32_settled;  /* 1 once the controller holds the instance's count
+                            (after fp32_adapt_sweeps sweeps)                    */
 } bss_stats;
 
 /* Per-kernel launch timing collected under BSS_FLAG_PROFILE. */

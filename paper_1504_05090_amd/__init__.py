@@ -38,7 +38,7 @@ class Options(ctypes.Structure):
                 ("n_stab", ctypes.c_int32), ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("flags", ctypes.c_uint32), ("drift_abort", ctypes.c_double),
                 ("trace_sweeps", ctypes.c_int32), ("fp32_slices", ctypes.c_int32),
-                ("fp32_drift_target", ctypes.c_double)]
+                ("fp32_drift_target", ctypes.c_double), ("fp32_adapt_sweeps", ctypes.c_int32)]
 
 
 class Instance(ctypes.Structure):
@@ -62,7 +62,7 @@ class Stats(ctypes.Structure):
                 ("fp32_slices", ctypes.c_int32), ("drift_rel_max", ctypes.c_double),
                 ("drift_rel_mean", ctypes.c_double), ("sweep_graph", ctypes.c_int32), ("shards", ctypes.c_int32),
                 ("fp32_fraction", ctypes.c_double), ("fp32_rejected", ctypes.c_int64),
-                ("fp32_fused", ctypes.c_int32)]
+                ("fp32_fused", ctypes.c_int32), ("fp32_settled", ctypes.c_int32)]
 
 
 class TuneResult(ctypes.Structure):
@@ -150,7 +150,8 @@ def _ptr(a: np.ndarray):
 
 
 def make_options(precision="fp64", delay_k=0, n_stab=0, flags=0, trace_sweeps=0, drift_abort=None,
-                 stream=None, workspace=None, workspace_bytes=0, fp32_slices=0, fp32_drift_target=0.0) -> Options:
+                 stream=None, workspace=None, workspace_bytes=0, fp32_slices=0, fp32_drift_target=0.0,
+                 fp32_adapt_sweeps=0) -> Options:
     """bss_options from the library's defaults; drift_abort=None keeps the
     library's default."""
     o = Options()
@@ -162,6 +163,7 @@ def make_options(precision="fp64", delay_k=0, n_stab=0, flags=0, trace_sweeps=0,
         o.drift_abort = drift_abort
     o.fp32_slices = fp32_slices
     o.fp32_drift_target = fp32_drift_target
+    o.fp32_adapt_sweeps = fp32_adapt_sweeps
     o.stream = stream
     o.workspace = workspace
     o.workspace_bytes = workspace_bytes
@@ -177,7 +179,7 @@ class Context:
     """
 
     def __init__(self, instances, precision="fp64", delay_k=0, n_stab=0, flags=0, trace_sweeps=0,
-                 drift_abort=None, stream=None, fp32_slices=0, fp32_drift_target=0.0):
+                 drift_abort=None, stream=None, fp32_slices=0, fp32_drift_target=0.0, fp32_adapt_sweeps=0):
         import torch  # device memory and streams only
 
         if not torch.cuda.is_available():
@@ -192,7 +194,7 @@ class Context:
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         opt = make_options(precision, delay_k, n_stab, flags, trace_sweeps, drift_abort,
                            stream=self._stream.cuda_stream, fp32_slices=fp32_slices,
-                           fp32_drift_target=fp32_drift_target)
+                           fp32_drift_target=fp32_drift_target, fp32_adapt_sweeps=fp32_adapt_sweeps)
         nbytes = ctypes.c_size_t()
         self._check(L.bss_workspace_size(arr, len(instances), ctypes.byref(opt), ctypes.byref(nbytes)),
                     "bss_workspace_size")

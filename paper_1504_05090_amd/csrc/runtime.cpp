@@ -57,6 +57,8 @@ struct Shard {
   int m32 = 0;                           // FP32 slices at the end of each block (mixed mode)
   int m32_max = 0;                       // automatic count, the controller's ceiling
   bool adapt = false;                    // mixed mode, automatic count: adjusted after every sweep
+  bool settled = false;                  // the controller's count is held (fp32_adapt_sweeps reached)
+  int adapted = 0;                       // sweeps the controller has adjusted the count after
   bool fused = false;                    // an FP32 ratio <= 0 was met: FP64 from then on
   int64_t fp32_rej_seen = 0;             // rejected FP32 ratios already acted on
   int64_t slices_run = 0, fp32_run = 0;  // slices swept since the last statistics reset, in FP32
@@ -249,7 +251,9 @@ int auto_fp32_slices(double lambda, int n_stab) {
 // (the FP32 drift controller, BSS_FLAG_NO_GRAPH, BSS_FLAG_PROFILE) keeps one
 // shard: with four, its eight streams share the process's four hardware
 // queues, and the sweep took 78 to 104 ms from run to run, against 73 ms with
-// one (mixed, the same workload).  A batch of several instances already
+// one (mixed, the same workload).  A controller context keeps its one shard
+// after it settles and its sweeps are captured, so that the held sweeps launch
+// the same kernels as the adapting ones.  A batch of several instances already
 // overlaps its instances and keeps one shard each.  The environment variable
 // BSS_SHARDS = 1..8 overrides, for tuning.
 int shard_count(int C, int n_instances, bool direct) {
@@ -369,6 +373,7 @@ bool check_options(const bss_options *o, std::string &why) {
   if (o->fp32_slices < 0) { why = "fp32_slices must be >= 0"; return false; }
   if (!(o->drift_abort >= 0.0)) { why = "drift_abort must be >= 0"; return false; }
   if (!(o->fp32_drift_target >= 0.0)) { why = "fp32_drift_target must be >= 0"; return false; }
+  if (o->fp32_adapt_sweeps < 0) { why = "fp32_adapt_sweeps must be >= 0"; return false; }
   return true;
 }
 
@@ -569,7 +574,7 @@ struct Exec {
     // FP32 slices of the drift controller: a finite ratio <= 0 (FP32 rounding
     // of a G with large entries) is rejected and counted; the controller then
     // runs the instance in FP64
-    a.fp32_guard = (!I.cur64 && I.adapt && a.trace_mode != 2) ? 1 : 0;
+    a.fp32_guard = (!I.cur64 && (I.adapt || I.settled) && a.trace_mode != 2) ? 1 : 0;
     a.trace = U.trace; a.trace_base = U.trace_base; a.trace_sweeps = U.trace_cap;
     a.stats = I.stats; a.err = c->err;
     Timed tm(c, I.cur64 ? F_FLIP64 : F_FLIP32, s);
@@ -1047,6 +1052,10 @@ int fp32_count(const Shard &I) {
 // < target / 2, e^{2 lambda} being the growth one more FP32 slice brings
 // (the spread of a slice's diagonal factors amplifies an earlier rounding
 // error once per wrap).  G is then converted to the precision slice 1 needs.
+// With fp32_adapt_sweeps = n > 0 an instance stops adapting after the n-th
+// adjusted sweep and holds its count from then on ("settled"): its sweeps can
+// then be captured like those of a fixed count, and it keeps the FP32 guard
+// (settled_fuse applies the fuse to it).
 bss_status adapt_fp32(bss_ctx *c) {
   bool any = false;
   for (auto &I : c->sh) any = any || I.adapt;
@@ -1078,6 +1087,11 @@ bss_status adapt_fp32(bss_ctx *c) {
     if (d > 0.5 * target) next[k] = std::max(0, I.m32 - 1);
     else if (d * std::exp(2.0 * I.lambda) < 0.5 * target) next[k] = std::min(I.m32_max, I.m32 + 1);
     changed = changed || next[k] != I.m32;
+    I.adapted += 1;
+    if (c->opt.fp32_adapt_sweeps > 0 && I.adapted >= c->opt.fp32_adapt_sweeps) {
+      I.adapt = false;
+      I.settled = true;
+    }
   }
   if (!changed) return BSS_OK;
   HIP_TRY(c, fork(c));
@@ -1085,6 +1099,46 @@ bss_status adapt_fp32(bss_ctx *c) {
     Shard &I = c->sh[k];
     if (next[k] == I.m32) continue;
     I.m32 = next[k];
+    Exec x(c, I);
+    x.use_precision(1);
+    if (x.e != hipSuccess) return exec_failed(c, x);
+  }
+  HIP_TRY(c, join(c));
+  return BSS_OK;
+}
+
+// The fuse of settled instances: a ratio rejected in their FP32 slices since
+// the last look switches the instance to FP64, as the controller does after a
+// sweep.  Their sweeps may have been replayed from a captured graph of the
+// held counts; after a fuse the context launches directly, so that no second
+// set of counts is ever captured in it (see bss_sweep).  Runs at the start of
+// bss_sweep; waits for the work already issued.
+bss_status settled_fuse(bss_ctx *c) {
+  bool any = false;
+  for (auto &I : c->sh) any = any || (I.settled && I.m32 > 0);
+  if (!any) return BSS_OK;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<size_t> hit;
+  for (size_t k = 0; k < c->sh.size(); ++k) {
+    Shard &I = c->sh[k];
+    if (!I.settled || I.m32 == 0) continue;
+    std::vector<ChainStats> cs(I.C);
+    HIP_TRY(c, hipMemcpy(cs.data(), I.stats, sizeof(ChainStats) * I.C, hipMemcpyDeviceToHost));
+    int64_t rej = 0;
+    for (auto &x : cs) rej += x.fp32_rejected;
+    if (rej > I.fp32_rej_seen) {
+      I.fp32_rej_seen = rej;
+      I.settled = false;
+      I.fused = true;
+      hit.push_back(k);
+    }
+  }
+  if (hit.empty()) return BSS_OK;
+  c->graphs = false;
+  HIP_TRY(c, fork(c));
+  for (size_t k : hit) {
+    Shard &I = c->sh[k];
+    I.m32 = 0;
     Exec x(c, I);
     x.use_precision(1);
     if (x.e != hipSuccess) return exec_failed(c, x);
@@ -1103,17 +1157,19 @@ bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure) {
   if (n_sweeps < 0) return fail(c, BSS_E_INVALID_ARG, "n_sweeps must be >= 0");
   for (auto &I : c->sh)
     if (I.slice != 1) return fail(c, BSS_E_STATE, "an instance is part-way through a sweep");
-  bool adapt = false;
-  for (auto &I : c->sh) adapt = adapt || I.adapt;
-  // with the drift controller the FP32 slice counts may change after every
-  // sweep, so sweeps are issued one at a time, and launched directly: a
-  // process that had swept a controlled context through captured sweeps of
-  // several counts crashed in the HIP runtime when it went on to the next
-  // context (twice at the same point, cause not found), so captured sweeps
-  // are kept to contexts whose slice precisions never change
-  const int per = adapt ? 1 : std::max(1, n_sweeps);
-  for (int done = 0; done < n_sweeps; done += per) {
-    const int n = std::min(per, n_sweeps - done);
+  if ((st = settled_fuse(c)) != BSS_OK) return st;
+  for (int done = 0; done < n_sweeps;) {
+    // while the drift controller adapts, the FP32 slice counts may change
+    // after every sweep, so sweeps are issued one at a time, and launched
+    // directly: a process that had swept a controlled context through
+    // captured sweeps of several counts crashed in the HIP runtime when it
+    // went on to the next context (twice at the same point, cause not found),
+    // so a context captures sweeps only while its slice precisions no longer
+    // change (fixed counts, or counts held once settled) and at most one set
+    // of counts (a fuse after settling turns capture off)
+    bool adapt = false;
+    for (auto &I : c->sh) adapt = adapt || I.adapt;
+    const int n = adapt ? 1 : n_sweeps - done;
     const bss_ctx::SweepGraph *sg = (c->graphs && !measure && !adapt) ? sweep_graph(c) : nullptr;
     if (sg) {
       for (int sw = 0; sw < n; ++sw) {
@@ -1135,6 +1191,7 @@ bss_status bss_sweep(bss_ctx *c, int32_t n_sweeps, int32_t measure) {
       I.slices_run += (int64_t)n * I.Lam;
       I.fp32_run += (int64_t)n * fp32_count(I);
     }
+    done += n;
     if (adapt && (st = adapt_fp32(c)) != BSS_OK) return st;
   }
   return BSS_OK;
@@ -1305,6 +1362,7 @@ bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
   out->sign = 1;
   double dsum = 0, rsum = 0;
   int64_t dcnt = 0, run = 0, run32 = 0, negs = 0;
+  bool settled = true;
   for (int k = 0; k < U->count; ++k) {
     const Shard &I = c->sh[U->first + k];
     std::vector<ChainStats> cs(I.C);
@@ -1327,7 +1385,9 @@ bss_status bss_get_stats(bss_ctx *c, int32_t inst, bss_stats *out) {
     negs += x_negs(cs);
     for (auto &x : cs) out->fp32_rejected += x.fp32_rejected;
     out->fp32_fused = out->fp32_fused || I.fused;
+    settled = settled && I.settled;
   }
+  out->fp32_settled = settled ? 1 : 0;
   out->sign = (negs % 2) ? -1 : 1;
   out->fp32_fraction = run ? (double)run32 / (double)run : 0.0;
   out->drift_mean = dcnt ? dsum / dcnt : 0.0;

@@ -132,3 +132,43 @@ def test_autotune_rejects_invalid_arguments():
     assert L.bss_autotune(ctypes.byref(inst), ctypes.byref(o), 1e-6, 2, 2, None) == bss.BSS_E_INVALID_ARG
     bad = bss.Instance(5, 2.0, 0.25, 4.0, 0.5, 1, 2)
     assert L.bss_autotune(ctypes.byref(bad), ctypes.byref(o), 1e-6, 2, 2, ctypes.byref(res)) == bss.BSS_E_UNSUPPORTED
+
+
+STRUCTS = [("bss_options", bss.Options), ("bss_instance", bss.Instance), ("bss_stats", bss.Stats),
+           ("bss_kernel_time", bss.KernelTime), ("bss_tune_result", bss.TuneResult)]
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """Every ctypes mirror has the size and field offsets of its C struct, as
+    a C compiler lays it out from include/bssqmc.h."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "bssqmc.h"', "int main(void) {"]
+    for cname, py in STRUCTS:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        s, f, v = line.split()
+        got[(s, f)] = int(v)
+    for cname, py in STRUCTS:
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_settle_option_defaults_and_checks():
+    o = bss.make_options()
+    assert o.struct_size == ctypes.sizeof(bss.Options)
+    assert o.fp32_adapt_sweeps == 0
+    o = bss.make_options(precision="mixed", fp32_adapt_sweeps=-1)
+    assert _create(4, opt=ctypes.byref(o))[0] == bss.BSS_E_INVALID_ARG

@@ -589,3 +589,50 @@ def test_kronecker_hopping_lattice_sizes(L):
         assert np.array_equal(g.field(0, c), o.field()), c
         for s in range(2):
             assert rel(g.green(0, c, s), o.green(s)) < 1e-10, (c, s)
+
+
+def test_settled_controller_replays_match_direct_launches():
+    """Mixed precision with the automatic FP32 count and fp32_adapt_sweeps = 3:
+    the drift controller adjusts the count after each of the first three
+    sweeps and then holds it.  The sweeps after that are replayed from one
+    captured graph and give bit for bit what a NO_GRAPH twin gives; the held
+    count is the one the controller reached, FP32 slices keep running, and the
+    drift stays within the controller's target."""
+    import torch
+    L, U, beta, dtau, C = 8, 2.0, 10.0, 0.5, 8
+    inst = dict(L=L, U=U, t=T, beta=beta, dtau=dtau, seed=BASE_SEED, n_chains=C)
+    print("[gpu] settled controller: 8x8 mixed, automatic count, fp32_adapt_sweeps=3", flush=True)
+    kw = dict(precision="mixed", delay_k=16, n_stab=10, fp32_adapt_sweeps=3)
+    a = bss.Context([inst], stream=torch.cuda.Stream(), **kw)
+    b = bss.Context([inst], stream=torch.cuda.Stream(), flags=bss.FLAG_NO_GRAPH, **kw)
+
+    def same(tag):
+        for c in range(C):
+            assert np.array_equal(a.field(0, c), b.field(0, c)), (tag, c)
+            for s in range(2):
+                assert np.array_equal(a.green(0, c, s), b.green(0, c, s)), (tag, c, s)
+
+    for n in range(3):
+        a.sweep(1)
+        b.sweep(1)
+        sa = a.stats()
+        assert sa["fp32_settled"] == (1 if n == 2 else 0) and sa["sweep_graph"] == 0, (n, sa)
+    same("adapting")
+    m = a.stats()["fp32_slices"]
+    assert m >= 1
+    a.sweep(3)
+    b.sweep(3)
+    a.synchronize()
+    same("settled")
+    a.sweep(1, measure=True)
+    b.sweep(1, measure=True)
+    a.sweep(2)
+    b.sweep(2)
+    same("settled after a measured sweep")
+    sa, sb = a.stats(), b.stats()
+    print(f"[gpu] held count {m}: {sa}", flush=True)
+    assert sa["sweep_graph"] == 1 and sb["sweep_graph"] == 0
+    assert sa["fp32_settled"] == 1 and sa["fp32_slices"] == m and sa["fp32_fused"] == 0
+    assert sa["sweeps"] == 9 and sa["fp32_fraction"] > 0
+    assert sa["drift_rel_max"] < 1e-3
+    assert a.double_occ() == b.double_occ()
