@@ -50,13 +50,13 @@ HBM_PEAK = 8.0e12
 # otherwise null.
 TRAFFIC = {
     "dense": {
-        "qr_udv": (3.9507e9, "k_qr.hip", "489fc1e42855"),
-        "qr_solve": (2.9530e9, "k_qr.hip", "489fc1e42855"),
-        "flip_f64": (1.0869e9, "k_flip.hip", "f441bb0b7329"),
-        "flip_f32": (4.829e8, "k_flip.hip", "f441bb0b7329"),
+        "qr_udv": (3.9604e9, "k_qr.hip", "37e793146f60"),
+        "qr_solve": (2.9527e9, "k_qr.hip", "37e793146f60"),
+        "flip_f64": (1.1113e9, "k_flip.hip", "f441bb0b7329"),
+        "flip_f32": (4.870e8, "k_flip.hip", "f441bb0b7329"),
         # the FP64 NN GEMM kernel (wraps, block products and UDV products share it)
-        "wrap_f64": (4.525e8, "k_gemm.hip", "57c2c9444073"),
-        "gemm_f64": (4.525e8, "k_gemm.hip", "57c2c9444073"),
+        "wrap_f64": (4.503e8, "k_gemm.hip", "57c2c9444073"),
+        "gemm_f64": (4.503e8, "k_gemm.hip", "57c2c9444073"),
         "wrap_f32": (1.703e8, "k_gemm.hip", "57c2c9444073"),
     },
     "kronecker": {},

@@ -594,10 +594,13 @@ __device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int
   int *nmv = mv_to + S::NB;
   // a NaN norm ranks last, so that the comparison stays a strict total order
   // and the ranks of the remaining columns are a permutation of 0..N-c0-1
+  // (the counting loops read LDS words that every lane shares; unrolled, a
+  // group of reads is in flight at once instead of one read per step)
   if (t == 0) s.nuout[0] = 0.0;   // no column outside the panel
   for (int q = c0 + t; q < N; q += QT) {
     const double nq = rank_key(s.norms[q]);
     int r = 0;
+#pragma unroll 16
     for (int p = c0; p < N; ++p) r += ranks_before(rank_key(s.norms[p]), p, nq, q);
     rank[q] = r;
   }
@@ -608,38 +611,74 @@ __device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int
     if (r == w) s.nuout[0] = isnan(s.norms[q]) ? 0.0 : s.norms[q];   // largest norm left outside
     if (r < w && q >= c0 + w) {          // vacated position: k-th among them
       int k = 0;
+#pragma unroll 16
       for (int p = c0 + w; p < q; ++p) k += rank[p] < w;
       mv_to[k] = q;
     }
     if (r >= w && q < c0 + w) {          // displaced column: k-th among them
       int k = 0;
+#pragma unroll 16
       for (int p = c0; p < q; ++p) k += rank[p] >= w;
       mv_from[k] = q;
     }
   }
   if (t == 0) {
     int k = 0;
+#pragma unroll 16
     for (int p = c0; p < c0 + w; ++p) k += rank[p] >= w;
     *nmv = k;
   }
   __syncthreads();
   const int nd = min(*nmv, w);
   // stage chosen columns (all rows), move the displaced ones, write back
-  // the rows above the panel
-#pragma unroll 8
-  for (int e = t; e < N * w; e += QT) {
-    const int r = e / w, i = e % w;
-    s.V[(r >= c0 ? r - c0 : m + r) * LDV + i] = A[(long)r * N + src[i]];
+  // the rows above the panel.  The columns are strided in the row-major
+  // matrix, so each element is its own memory access: all of a thread's loads
+  // (at most GM) are issued before the first store, and each pass costs one
+  // global round trip instead of one per group of loads.
+  constexpr int GM = 32;
+  static_assert(S::MT * 16 * S::NB <= GM * QT, "a thread's share of a panel exceeds the gather registers");
+  {
+    double g[GM];
+#pragma unroll
+    for (int u = 0; u < GM; ++u) {
+      const int e = t + u * QT;
+      if (e < N * w) {
+        const int r = e / w, i = e % w;
+        g[u] = A[(long)r * N + src[i]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < GM; ++u) {
+      const int e = t + u * QT;
+      if (e < N * w) {
+        const int r = e / w, i = e % w;
+        s.V[(r >= c0 ? r - c0 : m + r) * LDV + i] = g[u];
+      }
+    }
   }
   int o_i = 0, o_d = 0;
   double n_i = 0.0, n_d = 0.0;
   if (t < w) { o_i = s.orig[src[t]]; n_i = s.norms[src[t]]; }
   if (t < nd) { o_d = s.orig[mv_from[t]]; n_d = s.norms[mv_from[t]]; }
   __syncthreads();
-#pragma unroll 8
-  for (int e = t; e < N * nd; e += QT) {
-    const int r = e / nd, i = e % nd;
-    A[(long)r * N + mv_to[i]] = A[(long)r * N + mv_from[i]];
+  {
+    double g[GM];
+#pragma unroll
+    for (int u = 0; u < GM; ++u) {
+      const int e = t + u * QT;
+      if (e < N * nd) {
+        const int r = e / nd, i = e % nd;
+        g[u] = A[(long)r * N + mv_from[i]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < GM; ++u) {
+      const int e = t + u * QT;
+      if (e < N * nd) {
+        const int r = e / nd, i = e % nd;
+        A[(long)r * N + mv_to[i]] = g[u];
+      }
+    }
   }
   if (t < nd) { s.orig[mv_to[t]] = o_d; s.norms[mv_to[t]] = n_d; }
   __syncthreads();
