@@ -149,3 +149,31 @@ def test_controller_fp32_ratio_fuse():
     assert st["fp32_fused"] == 1 and st["fp32_slices"] == 0
     g.sweep(2)
     assert g.stats()["fp32_slices"] == 0
+
+
+def test_settled_controller_fp32_ratio_fuse():
+    """A controller that has settled (fp32_adapt_sweeps) keeps the FP32 guard:
+    a non-positive ratio forced in an FP32 slice after settling is rejected
+    and counted; the next bss_sweep call switches the instance to FP64, and
+    the context goes on sweeping without capturing a second graph."""
+    g = make(L=8, beta=10.0, chains=2, precision="mixed", delay_k=16, n_stab=10, drift_abort=0.0,
+             fp32_adapt_sweeps=3)
+    g.sweep(3)                                   # the controller reaches 2 FP32 slices and settles
+    st = g.stats()
+    assert st["fp32_settled"] == 1 and st["fp32_slices"] == 2
+    g.sweep(2)                                   # replayed from the captured graph
+    assert g.stats()["sweep_graph"] == 1
+    g.step_slices(8)                             # slices 9 and 10 run in FP32
+    g.debug_set_green(5.0, chain=1, spin=1, i=20, j=20)
+    g.step_slices(12)                            # to the end of the sweep
+    st = g.stats()
+    assert st["fp32_rejected"] >= 1 and st["fp32_fused"] == 0 and st["fp32_settled"] == 1
+    g.sweep(1)                                   # the fuse is applied at the start of this call
+    st = g.stats()
+    print(f"[gpu] settled fuse: rejected {st['fp32_rejected']}, fused {st['fp32_fused']}, "
+          f"settled {st['fp32_settled']}, fp32_slices {st['fp32_slices']}", flush=True)
+    assert st["fp32_fused"] == 1 and st["fp32_settled"] == 0 and st["fp32_slices"] == 0
+    frac = st["fp32_fraction"]
+    g.sweep(2)
+    st = g.stats()
+    assert st["fp32_slices"] == 0 and st["fp32_fraction"] < frac and st["sweeps"] == 9
