@@ -51,7 +51,6 @@ HBM_PEAK = 8.0e12
 TRAFFIC = {
     "dense": {
         "qr_udv": (3.9604e9, "k_qr.hip", "37e793146f60"),
-        "qr_solve": (2.9527e9, "k_qr.hip", "37e793146f60"),
         "flip_f64": (1.1113e9, "k_flip.hip", "f441bb0b7329"),
         "flip_f32": (4.870e8, "k_flip.hip", "f441bb0b7329"),
         # the FP64 NN GEMM kernel (wraps, block products and UDV products share it)
@@ -84,8 +83,9 @@ def family_model(fam: str, N: int, mats: float, chains: float, acc: float, k: in
         return 2.0 * N ** 3 * mats, PEAK[fam[-3:]], "mfma"      # one batched N x N x N product
     if fam == "qr_udv":
         return (8.0 / 3.0) * N ** 3 * mats, PEAK["f64"], "mfma"  # Householder R (4/3 N^3) + explicit Q (4/3 N^3)
-    if fam == "qr_solve":
-        return (13.0 / 3.0) * N ** 3 * mats, PEAK["f64"], "mfma"  # R (4/3), Q^T on N columns (2), back substitution (1)
+    if fam == "lu_solve":
+        # LU (2/3 N^3), forward (N^3) and back (N^3) substitution on N right-hand sides
+        return (8.0 / 3.0) * N ** 3 * mats, PEAK["f64"], "mfma"
     if fam in ("flip_f32", "flip_f64"):
         # per chain and slice, both spins: rank-k flushes 4 a N^3, row/column
         # corrections 4 a N^2 k (a = acceptance)

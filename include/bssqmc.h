@@ -192,7 +192,7 @@ typedef struct {
 /* Per-kernel launch timing collected under BSS_FLAG_PROFILE. */
 typedef struct {
   char name[32];         /* kernel family: flip_f32, flip_f64, wrap_f32, wrap_f64,
-                            gemm_f64, qr_udv, qr_solve, elementwise,
+                            gemm_f64, qr_udv, lu_solve, elementwise,
                             drift_replace, measure                                */
   int64_t launches;
   double total_ms;       /* summed HIP-event durations                             */

@@ -136,7 +136,7 @@ hipError_t green_run(int32_t L, double U, double t, double beta, double dtau, in
   }
   // G = (D_b^{-1} U^T + D_s V)^{-1} D_b^{-1} U^T, solved into G_out
   chk(fresh_prep(base + p.U[cur], base + p.D[cur], base + p.V[cur], base + p.W1, nullptr, nullptr, G_out, 2, N, s));
-  chk(qr_solve_blocked(base + p.W1, G_out, base + p.Tq, 2, N, s));
+  chk(lu_solve_blocked(base + p.W1, G_out, 2, N, s));
   return e;
 }
 

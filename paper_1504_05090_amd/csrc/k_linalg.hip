@@ -1,144 +1,12 @@
-// FP64 stabilisation kernels: pre-pivoted Householder QR for the UDV
-// factorisation of the B chain (Loh & Gubernatis), the QR solve of the
-// scale-separated fresh-G system, and the drift/replace step.
-//
-// One workgroup factors one matrix; the matrix lives in global memory (L2 /
-// MALL resident) and the current Householder vector in LDS.  Pivoting is done
-// once up front (columns sorted by decreasing norm, Bai, Lee, Li & Xu 2011),
-// which orders the graded scales of X = P U D the way column pivoting would.
+// FP64 stabilisation kernels around the factorisations of k_qr.hip: the
+// scale-separated fresh-G system and its right-hand side, the right-hand side
+// of the time-displaced G, the drift/replace step and precision conversions.
 #include "common.h"
 #include "kernels.h"
 
 namespace bss {
 
 namespace {
-constexpr int QT = 256;      // threads per factorisation
-constexpr int NMAX = 512;
-
-// Householder reflector of column j of W (rows j..N-1): W[j:,j] -> alpha e_1.
-// Leaves v in vcur[j..N-1] and returns tau; alpha in *alpha.
-__device__ double householder_col(const double *W, int N, int j, double *vcur, double *red, double *alpha) {
-  double part = 0.0;
-  for (int r = j + threadIdx.x; r < N; r += blockDim.x) {
-    const double x = W[(long)r * N + j];
-    vcur[r] = x;
-    part += x * x;
-  }
-  const double nrm2 = block_sum(part, red);
-  const double x0 = vcur[j];
-  const double a = x0 > 0.0 ? -sqrt(nrm2) : sqrt(nrm2);
-  const double v0 = x0 - a;
-  const double vn2 = nrm2 - x0 * x0 + v0 * v0;
-  __syncthreads();
-  if (threadIdx.x == 0) vcur[j] = v0;
-  __syncthreads();
-  *alpha = a;
-  return vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-}
-
-// X (overwritten with the factor) -> U = Q, D = diag R, RP = D^{-1} R Pi^T.
-__global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Uall, double *Dall, double *RPall, int N) {
-  __shared__ double norms[NMAX], vcur[NMAX], vhead[NMAX], tau[NMAX], rdiag[NMAX];
-  __shared__ int perm[NMAX];
-  __shared__ double red[16];
-  const long NN = (long)N * N, b = blockIdx.x;
-  double *X = Xall + b * NN, *U = Uall + b * NN, *RP = RPall + b * NN, *D = Dall + b * N;
-  double *W = RP;   // the permuted copy is factored in the RP buffer, RP written last
-  const int t = threadIdx.x, nt = blockDim.x;
-
-  for (int q = t; q < N; q += nt) {
-    double s = 0.0;
-    for (int r = 0; r < N; ++r) { const double x = X[(long)r * N + q]; s += x * x; }
-    norms[q] = s;
-  }
-  __syncthreads();
-  for (int q = t; q < N; q += nt) {
-    int rank = 0;
-    const double nq = norms[q];
-    for (int p = 0; p < N; ++p) rank += (norms[p] > nq) || (norms[p] == nq && p < q);
-    perm[rank] = q;
-  }
-  __syncthreads();
-  for (long e = t; e < NN; e += nt) W[e] = X[(e / N) * N + perm[e % N]];
-  __syncthreads();
-
-  for (int j = 0; j < N; ++j) {
-    double alpha;
-    const double tj = householder_col(W, N, j, vcur, red, &alpha);
-    if (t == 0) { tau[j] = tj; vhead[j] = vcur[j]; rdiag[j] = alpha; }
-    if (tj != 0.0) {
-      for (int q = j + 1 + t; q < N; q += nt) {
-        double wq = 0.0;
-        for (int r = j; r < N; ++r) wq += vcur[r] * W[(long)r * N + q];
-        wq *= tj;
-        for (int r = j; r < N; ++r) W[(long)r * N + q] -= wq * vcur[r];
-      }
-    }
-    __syncthreads();
-  }
-  // Q = H_0 H_1 ... H_{N-1}: apply the reflectors to I from the last one
-  for (long e = t; e < NN; e += nt) U[e] = ((e / N) == (e % N)) ? 1.0 : 0.0;
-  __syncthreads();
-  for (int j = N - 1; j >= 0; --j) {
-    for (int r = j + 1 + t; r < N; r += nt) vcur[r] = W[(long)r * N + j];
-    if (t == 0) vcur[j] = vhead[j];
-    __syncthreads();
-    const double tj = tau[j];
-    if (tj != 0.0) {
-      for (int q = j + t; q < N; q += nt) {
-        double wq = 0.0;
-        for (int r = j; r < N; ++r) wq += vcur[r] * U[(long)r * N + q];
-        wq *= tj;
-        for (int r = j; r < N; ++r) U[(long)r * N + q] -= wq * vcur[r];
-      }
-    }
-    __syncthreads();
-  }
-  // D and RP = D^{-1} R Pi^T:  RP[i][perm[q]] = R[i][q] / R[i][i]
-  for (int i = t; i < N; i += nt) D[i] = rdiag[i];
-  // X is free now: build RP there, then copy (W and RP share storage)
-  for (long e = t; e < NN; e += nt) {
-    const int i = (int)(e / N), q = (int)(e % N);
-    const double v = q < i ? 0.0 : (q == i ? 1.0 : W[e] / rdiag[i]);
-    X[(long)i * N + perm[q]] = v;
-  }
-  __syncthreads();
-  for (long e = t; e < NN; e += nt) RP[e] = X[e];
-}
-
-// Solve M Z = B (N right-hand sides) by Householder QR of M.
-__global__ __launch_bounds__(QT) void k_qr_solve(double *Mall, double *Ball, int N) {
-  __shared__ double vcur[NMAX], rdiag[NMAX];
-  __shared__ double red[16];
-  const long NN = (long)N * N, b = blockIdx.x;
-  double *M = Mall + b * NN, *B = Ball + b * NN;
-  const int t = threadIdx.x, nt = blockDim.x;
-  for (int j = 0; j < N; ++j) {
-    double alpha;
-    const double tj = householder_col(M, N, j, vcur, red, &alpha);
-    if (t == 0) rdiag[j] = alpha;
-    if (tj != 0.0) {
-      // trailing columns of M (q > j) and every column of B
-      for (int q = j + 1 + t; q < 2 * N; q += nt) {
-        double *col = q < N ? M + q : B + (q - N);
-        double wq = 0.0;
-        for (int r = j; r < N; ++r) wq += vcur[r] * col[(long)r * N];
-        wq *= tj;
-        for (int r = j; r < N; ++r) col[(long)r * N] -= wq * vcur[r];
-      }
-    }
-    __syncthreads();
-  }
-  // back substitution R Z = Q^T B, one column of B per thread
-  for (int q = t; q < N; q += nt) {
-    for (int i = N - 1; i >= 0; --i) {
-      double s = B[(long)i * N + q];
-      for (int c = i + 1; c < N; ++c) s -= M[(long)i * N + c] * B[(long)c * N + q];
-      B[(long)i * N + q] = s / rdiag[i];
-    }
-  }
-}
-
 // M = Db_R^{-1} (U_R^T U_L) Db_L^{-1} + Ds_R (V_R V_L^T) Ds_L   (W1 in, M out)
 // or, without a left factor,  M = Db_R^{-1} U_R^T + Ds_R V_R;
 // RHS = Db_R^{-1} U_R^T.
@@ -248,18 +116,6 @@ __global__ void k_convert(const Ts *src, Td *dst, long n) {
   if (e < n) dst[e] = (Td)src[e];
 }
 }  // namespace
-
-hipError_t qr_udv(double *X, double *U, double *D, double *RP, int mats, int N, hipStream_t s) {
-  if (N > NMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_qr_udv, dim3(mats), dim3(QT), 0, s, X, U, D, RP, N);
-  return hipGetLastError();
-}
-
-hipError_t qr_solve(double *M, double *B, int mats, int N, hipStream_t s) {
-  if (N > NMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_qr_solve, dim3(mats), dim3(QT), 0, s, M, B, N);
-  return hipGetLastError();
-}
 
 hipError_t fresh_prep(const double *UR, const double *DR, const double *VR, double *W1, const double *W2,
                       const double *DL, double *RHS, int mats, int N, hipStream_t s) {

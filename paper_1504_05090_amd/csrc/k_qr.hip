@@ -21,7 +21,11 @@
 // as it does for unblocked Businger-Golub pivoting.
 //
 //   qr_udv:   X Pi = Q R  ->  U = Q, D = diag R, RP = D^{-1} R Pi^T
-//   qr_solve: M Z = B by M = Q R (no pivoting), Z = R^{-1} Q^T B
+//
+// The file also holds the solve of the fresh-G system by blocked LU with
+// partial pivoting (k_lu_solve), which shares the LDS layout and the blocked
+// back substitution:
+//   lu_solve: P M = L U,  Z = U^-1 L^-1 P B
 #include "common.h"
 #include "kernels.h"
 #include "qr_order.h"
@@ -700,10 +704,10 @@ __device__ __forceinline__ void select_panel(const Lds &s, double *A, int N, int
 // factor A (N x N, in place) panel by panel.  Panel k's T (w_k x w_k,
 // packed) is saved to Tsave at the sum of the earlier w_j^2, and with PIVOT
 // its start and width to plist[2k], plist[2k + 1] (panels have variable
-// width there).  B: reflectors also applied to B's nrhs columns (solve).
+// width there).
 // Returns the number of panels.
 template <class S, bool PIVOT>
-__device__ __forceinline__ int factor(const Lds &s, double *A, double *Tsave, int *plist, int N, double *B, int nrhs) {
+__device__ __forceinline__ int factor(const Lds &s, double *A, double *Tsave, int *plist, int N) {
   constexpr int NB = S::NB, LDV = S::LDV;
   int c0 = 0, np = 0;
   long toff = 0;
@@ -756,7 +760,6 @@ __device__ __forceinline__ int factor(const Lds &s, double *A, double *Tsave, in
     build_T<S>(s, m, weff, mr);
     for (int e = threadIdx.x; e < weff * weff; e += QT) Tsave[toff + e] = s.T[(e / weff) * NB + e % weff];
     if (c0 + w < N) apply<S, true, PIVOT>(s, A, N, c0, m, mr, c0 + w, N, weff);
-    if (B) apply<S, true, false>(s, B, nrhs, c0, m, mr, 0, nrhs, 0);
     toff += (long)weff * weff;
     c0 += weff;
     ++np;
@@ -792,7 +795,7 @@ __global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long 
     }
     __syncthreads();   // the panel selection reads every column's norm
   }
-  const int np = factor<S, true>(s, X, Ts, plist, N, nullptr, 0);
+  const int np = factor<S, true>(s, X, Ts, plist, N);
   // D = diag R,  RP[i][orig[q]] = R[i][q] / R[i][i]
   for (int i = t; i < N; i += QT) D[i] = X[(long)i * N + i];
   // eight elements' loads in flight per step
@@ -836,16 +839,14 @@ __global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long 
   }
 }
 
+// Back substitution U Z = Y in place of Y (B), U upper triangular in M (row
+// i of U in row mrow(i) of M; the identity unless `rowmap` is given), block
+// rows of NB from the bottom: the block row of U right of the diagonal block
+// is staged in LDS for the MFMA update, the diagonal block solved per column.
 template <class S>
-__global__ __launch_bounds__(QT) void k_qr_solve(double *Mall, double *Ball, double *Tall, long tstride, int N) {
+__device__ __forceinline__ void back_substitute(const Lds &s, const double *M, double *B, int N, const int *rowmap) {
   constexpr int NB = S::NB;
-  extern __shared__ double smem[];
-  const Lds s = carve<S>((char *)smem, N);
-  const long NN = (long)N * N, b = blockIdx.x;
-  double *M = Mall + b * NN, *B = Ball + b * NN;
-  double *Ts = Tall + b * tstride;
-  factor<S, false>(s, M, Ts, nullptr, N, B, N);
-  // back substitution R Z = Y (Y = Q^T B in B), block rows from the bottom
+  auto mrow = [&](int i) { return rowmap ? rowmap[i] : i; };
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
   const int np = (N + NB - 1) / NB;
@@ -861,7 +862,7 @@ __global__ __launch_bounds__(QT) void k_qr_solve(double *Mall, double *Ball, dou
 #pragma unroll 8
       for (int e = t; e < NB * kn; e += QT) {
         const int i = e / kn, k = e % kn;
-        const double a = M[(long)(r0 + min(i, w - 1)) * N + k0 + k];
+        const double a = M[(long)mrow(r0 + min(i, w - 1)) * N + k0 + k];
         Rs[i * RLD + k] = (i < w) ? a : 0.0;
       }
       __syncthreads();
@@ -902,7 +903,7 @@ __global__ __launch_bounds__(QT) void k_qr_solve(double *Mall, double *Ball, dou
     }
     for (int e = t; e < NB * NB; e += QT) {
       const int i = e / NB, q = e % NB;
-      Rd[e] = (i < w && q < w) ? M[(long)(r0 + i) * N + r0 + q] : 0.0;
+      Rd[e] = (i < w && q < w) ? M[(long)mrow(r0 + i) * N + r0 + q] : 0.0;
     }
     __syncthreads();
     for (int q = t; q < N; q += QT) {   // one right-hand side column per thread
@@ -924,6 +925,292 @@ __global__ __launch_bounds__(QT) void k_qr_solve(double *Mall, double *Ball, dou
     }
     __syncthreads();
   }
+}
+
+// Solve M Z = B by LU with partial pivoting: Z in B, M overwritten by its
+// factors; one workgroup per matrix.  Right-looking, in panels of NB columns.
+// Rows are never moved: perm[i] (LDS) is the row of M and B that holds
+// logical row i.  A panel is factored in LDS in the order its rows were
+// loaded, each pivot chosen among the rows not yet chosen (largest |a|, a NaN
+// last, ties to the lower position: the order of qr_order.h), and stored back
+// to the rows it came from.  B's columns go along as further columns of the
+// trailing matrix, so after the last panel B holds L^-1 P B; its rows are
+// then put in logical order and U Z = L^-1 P B is solved by back_substitute
+// with U's rows read through perm.
+template <class S>
+__global__ __launch_bounds__(QT) void k_lu_solve(double *Mall, double *Ball, int N) {
+  constexpr int NB = S::NB, LDV = S::LDV;
+  constexpr int RPT = S::MT * 16 / QT;   // panel rows per thread (1 or 2)
+  static_assert(RPT * QT == S::MT * 16, "panel rows not divisible over the threads");
+  extern __shared__ double smem[];
+  const Lds s = carve<S>((char *)smem, N);
+  const long NN = (long)N * N, b = blockIdx.x;
+  double *M = Mall + b * NN, *B = Ball + b * NN;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int l16 = lane & 15, lq = lane >> 4;
+  int *perm = s.orig;        // [N] logical row -> stored row
+  int *lrow = s.sel;         // [NB] panel position of the j-th pivot
+  int *loc = s.sel + NB;     // [N] panel position of the i-th row left after the panel
+  int *redi = loc + N;       // [4] pivot candidates by wavefront
+  int *cnt = redi + 4;       // [4] rows left per wavefront
+  double *redv = s.red;      // [4]
+  double *L11 = s.T;         // [NB][NB] the panel's unit lower block, logical order
+  for (int i = t; i < N; i += QT) perm[i] = i;
+  __syncthreads();
+  // a thread's share of an N x NB block (panel loads, the reordering of B):
+  // all of its loads are issued before the first store
+  constexpr int GM = S::MT * 16 * NB / QT;
+  double g[GM];
+  for (int c0 = 0; c0 < N; c0 += NB) {
+    const int w = min(NB, N - c0), m = N - c0, mt = m - w;
+#pragma unroll
+    for (int u = 0; u < GM; ++u) {
+      const int e = t + u * QT, r = e / NB, q = e % NB;
+      g[u] = (r < m && q < w) ? M[(long)perm[c0 + r] * N + c0 + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < GM; ++u) {
+      const int e = t + u * QT, r = e / NB, q = e % NB;
+      if (r < m) s.V[r * LDV + q] = g[u];
+    }
+    __syncthreads();
+    // unblocked LU of the panel: a thread holds its rows in registers (the
+    // column steps unrolled, so that every index is static); per step the
+    // candidates meet through LDS, the chosen row is published there, and
+    // the other rows take their multipliers and updates from it
+    double rv[RPT][NB];
+    bool chosen[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      chosen[k] = false;
+      const int r = t + k * QT;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) rv[k][q] = r < m ? s.V[r * LDV + q] : 0.0;
+    }
+    double *prow = s.Wp;   // [NB] the pivot row of the current step
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      if (j < w) {
+        double best = -1.0;
+        int bi = 0x7fffffff;
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          const int r = t + k * QT;
+          if (r < m && !chosen[k]) {
+            const double key = rank_key(fabs(rv[k][j]));
+            if (ranks_before(key, r, best, bi)) { best = key; bi = r; }
+          }
+        }
+        auto take = [&](double ob, int op) {
+          if (ranks_before(ob, op, best, bi)) { best = ob; bi = op; }
+        };
+        take(dpp_dbl<DPP_XOR1>(best), dpp_int<DPP_XOR1>(bi));
+        take(dpp_dbl<DPP_XOR2>(best), dpp_int<DPP_XOR2>(bi));
+        take(dpp_dbl<DPP_HALF_MIRROR>(best), dpp_int<DPP_HALF_MIRROR>(bi));
+        take(dpp_dbl<DPP_MIRROR>(best), dpp_int<DPP_MIRROR>(bi));
+        take(__shfl_xor(best, 16, 64), __shfl_xor(bi, 16, 64));
+        take(__shfl_xor(best, 32, 64), __shfl_xor(bi, 32, 64));
+        if (lane == 0) { redv[wv] = best; redi[wv] = bi; }
+        __syncthreads();
+        double pb = redv[0];
+        int P = redi[0];
+#pragma unroll
+        for (int q = 1; q < 4; ++q)
+          if (ranks_before(redv[q], redi[q], pb, P)) { pb = redv[q]; P = redi[q]; }
+        if (t == 0) lrow[j] = P;
+#pragma unroll
+        for (int k = 0; k < RPT; ++k)
+          if (t + k * QT == P) {
+            chosen[k] = true;
+#pragma unroll
+            for (int q = j; q < NB; ++q) prow[q] = rv[k][q];
+          }
+        __syncthreads();
+        const double piv = prow[j];
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          const int r = t + k * QT;
+          if (r < m && !chosen[k]) {
+            const double l = rv[k][j] / piv;
+            rv[k][j] = l;
+#pragma unroll
+            for (int q = j + 1; q < NB; ++q) rv[k][q] -= l * prow[q];
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int r = t + k * QT;
+      if (r < m) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) s.V[r * LDV + q] = rv[k][q];
+      }
+    }
+    __syncthreads();
+    // the rows left, in panel order, follow the pivots
+    int before = 0;
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int r = t + k * QT;
+      const bool left = r < m && !chosen[k];
+      const unsigned long long bal = __ballot(left);
+      if (lane == 0) cnt[wv] = __popcll(bal);
+      __syncthreads();
+      int off = before;
+      for (int q = 0; q < wv; ++q) off += cnt[q];
+      if (left) loc[off + __popcll(bal & ((1ull << lane) - 1ull))] = r;
+      for (int q = 0; q < 4; ++q) before += cnt[q];
+      __syncthreads();
+    }
+    // store the factored panel to its rows, the unit lower block in logical
+    // order, then the new logical order of the rows c0..N-1
+    for (int e = t; e < m * w; e += QT) {
+      const int r = e / w, q = e % w;
+      M[(long)perm[c0 + r] * N + c0 + q] = s.V[r * LDV + q];
+    }
+    for (int e = t; e < NB * NB; e += QT) {
+      const int i = e / NB, q = e % NB;
+      L11[e] = (i < w && q < i) ? s.V[lrow[i] * LDV + q] : 0.0;
+    }
+    int np[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = t + k * QT;
+      np[k] = i < m ? perm[c0 + (i < w ? lrow[i] : loc[i - w])] : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+      const int i = t + k * QT;
+      if (i < m) perm[c0 + i] = np[k];
+    }
+    __syncthreads();
+    // L11^-1 (unit lower) into LDS, one column per thread of the first
+    // wavefront by forward substitution (L11 is zero beyond w x w, so the
+    // inverse is the identity there)
+    double *Li = s.W2;   // [NB][NB]
+    if (t < NB) {
+      double y[NB];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        double acc = i == t ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc -= L11[i * NB + k] * y[k];
+        y[i] = acc;
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) Li[i * NB + t] = y[i];
+    }
+    __syncthreads();
+    // U12 = L11^-1 A12 for M's columns right of the panel and B's columns, on
+    // FP64 MFMA: a wavefront holds a 16-column tile of A12 and overwrites it
+    const int ncm = N - c0 - w;
+    {
+      const int tiles_m = (ncm + 15) / 16, tiles = tiles_m + (N + 15) / 16;
+      for (int tc = wv; tc < tiles; tc += QT / 64) {
+        double *A = tc < tiles_m ? M : B;
+        const int cl = (tc < tiles_m ? tc : tc - tiles_m) * 16 + l16;
+        const bool cin = cl < (tc < tiles_m ? ncm : N);
+        const int col = tc < tiles_m ? c0 + w + cl : cl;
+        double bz[NB / 4];
+#pragma unroll
+        for (int u = 0; u < NB / 4; ++u) {
+          const int k = 4 * u + lq;
+          bz[u] = (cin && k < w) ? A[(long)perm[c0 + k] * N + col] : 0.0;
+        }
+        M64::acc_t cv[NB / 16];
+#pragma unroll
+        for (int q = 0; q < NB / 16; ++q) {
+          cv[q] = M64::acc_t{0, 0, 0, 0};
+#pragma unroll
+          for (int u = 0; u < NB / 4; ++u) cv[q] = M64::mac(Li[(q * 16 + l16) * NB + 4 * u + lq], bz[u], cv[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NB / 16; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = q * 16 + M64::row(lane, r);
+            if (row < w && cin) A[(long)perm[c0 + row] * N + col] = cv[q][r];
+          }
+      }
+    }
+    __syncthreads();
+    // trailing update A22 -= L21 U12 on FP64 MFMA: 16-column tiles per
+    // wavefront; a tile's rows are loaded together, RC row tiles at a time,
+    // and the products (-L21 from the panel in LDS, U12 held in registers)
+    // accumulate into them
+    if (mt > 0) {
+      constexpr int RC = S::MT < 16 ? S::MT : 16;
+      const int tiles_m = (ncm + 15) / 16, tiles = tiles_m + (N + 15) / 16;
+      const int rtiles = (mt + 15) / 16;
+      for (int tc = wv; tc < tiles; tc += QT / 64) {
+        double *A = tc < tiles_m ? M : B;
+        const int cl = (tc < tiles_m ? tc : tc - tiles_m) * 16 + l16;
+        const bool cin = cl < (tc < tiles_m ? ncm : N);
+        const int col = tc < tiles_m ? c0 + w + cl : cl;
+        double bz[NB / 4];
+#pragma unroll
+        for (int u = 0; u < NB / 4; ++u) {
+          const int k = 4 * u + lq;
+          bz[u] = (cin && k < w) ? A[(long)perm[c0 + k] * N + col] : 0.0;
+        }
+        for (int t0 = 0; t0 < rtiles; t0 += RC) {
+          M64::acc_t cv[RC];
+#pragma unroll
+          for (int q = 0; q < RC; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = (t0 + q) * 16 + M64::row(lane, r);
+              cv[q][r] = (row < mt && cin) ? A[(long)perm[c0 + w + row] * N + col] : 0.0;
+            }
+#pragma unroll
+          for (int q = 0; q < RC; ++q) {
+            if (t0 + q < rtiles) {
+              const int arow = (t0 + q) * 16 + l16;
+              const int ar = arow < mt ? loc[arow] : 0;
+#pragma unroll
+              for (int u = 0; u < NB / 4; ++u) {
+                const int k = 4 * u + lq;
+                const double a = (arow < mt && k < w) ? -s.V[ar * LDV + k] : 0.0;
+                cv[q] = M64::mac(a, bz[u], cv[q]);
+              }
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < RC; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = (t0 + q) * 16 + M64::row(lane, r);
+              if (row < mt && cin) A[(long)perm[c0 + w + row] * N + col] = cv[q][r];
+            }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // B's rows into logical order, NB columns at a time through LDS
+  for (int cb = 0; cb < N; cb += NB) {
+#pragma unroll
+    for (int u = 0; u < GM; ++u) {
+      const int e = t + u * QT, i = e / NB, c = e % NB;
+      g[u] = (i < N && cb + c < N) ? B[(long)perm[i] * N + cb + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < GM; ++u) {
+      const int e = t + u * QT;
+      if (e < N * NB) s.V[e] = g[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < GM; ++u) {
+      const int e = t + u * QT, i = e / NB, c = e % NB;
+      g[u] = e < N * NB ? s.V[e] : 0.0;
+      if (i < N && cb + c < N) B[(long)i * N + cb + c] = g[u];
+    }
+    __syncthreads();
+  }
+  back_substitute<S>(s, M, B, N, perm);
 }
 
 constexpr int SMALL_MAX_N = 256;
@@ -951,14 +1238,15 @@ hipError_t qr_udv_blocked(double *X, double *Scr, double *Tsave, double *U, doub
   return hipGetLastError();
 }
 
-hipError_t qr_solve_blocked(double *M, double *B, double *Tsave, int mats, int N, hipStream_t s) {
+hipError_t lu_solve_blocked(double *M, double *B, int mats, int N, hipStream_t s) {
   if (N > 512) return hipErrorInvalidValue;
-  const long ts = (long)qr_tsave_doubles(N);
+  if ((N <= SMALL_MAX_N ? lds_bytes<ShapeS>(N) : lds_bytes<ShapeL>(N)) > 160 * 1024) return hipErrorInvalidValue;
   if (N <= SMALL_MAX_N)
-    hipLaunchKernelGGL(k_qr_solve<ShapeS>, dim3(mats), dim3(QT), lds_bytes<ShapeS>(N), s, M, B, Tsave, ts, N);
+    hipLaunchKernelGGL(k_lu_solve<ShapeS>, dim3(mats), dim3(QT), lds_bytes<ShapeS>(N), s, M, B, N);
   else
-    hipLaunchKernelGGL(k_qr_solve<ShapeL>, dim3(mats), dim3(QT), lds_bytes<ShapeL>(N), s, M, B, Tsave, ts, N);
+    hipLaunchKernelGGL(k_lu_solve<ShapeL>, dim3(mats), dim3(QT), lds_bytes<ShapeL>(N), s, M, B, N);
   return hipGetLastError();
 }
+
 
 }  // namespace bss

@@ -91,19 +91,16 @@ hipError_t copy_to_bulk(const double *src, void *dst, long n, bool fp64, hipStre
 hipError_t bump_counter(int64_t *ctr, hipStream_t s);
 
 // FP64 stabilisation
-// Pre-pivoted Householder QR of X (overwritten): U = Q, D = diag(R),
-// RP = D^{-1} R Pi^T (so that X = U diag(D) RP).
-hipError_t qr_udv(double *X, double *U, double *D, double *RP, int mats, int N, hipStream_t s);
-// Blocked variants (compact WY, MFMA trailing updates).  Tsave holds
-// qr_tsave_doubles(N) and Scr qr_scratch_doubles(N) doubles per matrix; the
-// input X of qr_udv_blocked is overwritten.
+// Blocked Householder QR with Businger-Golub pivoting of X (overwritten):
+// U = Q, D = diag(R), RP = D^{-1} R Pi^T (so that X = U diag(D) RP).  Tsave
+// holds qr_tsave_doubles(N) and Scr qr_scratch_doubles(N) doubles per matrix.
 size_t qr_tsave_doubles(int N);
 size_t qr_scratch_doubles(int N);
 hipError_t qr_udv_blocked(double *X, double *Scr, double *Tsave, double *U, double *D, double *RP, int mats, int N,
                           hipStream_t s);
-hipError_t qr_solve_blocked(double *M, double *B, double *Tsave, int mats, int N, hipStream_t s);
-// M Z = B by Householder QR (M overwritten, B replaced by Z).
-hipError_t qr_solve(double *M, double *B, int mats, int N, hipStream_t s);
+// M Z = B by blocked LU with partial pivoting (M overwritten by its factors,
+// B replaced by Z); N <= 512.
+hipError_t lu_solve_blocked(double *M, double *B, int mats, int N, hipStream_t s);
 // Middle matrix of the two-sided fresh-G formula and its right-hand side.
 hipError_t fresh_prep(const double *UR, const double *DR, const double *VR, double *W1,
                       const double *W2, const double *DL, double *RHS, int mats, int N,

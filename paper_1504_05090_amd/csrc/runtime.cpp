@@ -157,10 +157,10 @@ struct bss_ctx {
 };
 
 namespace {
-enum KFam { F_FLIP32, F_FLIP64, F_WRAP32, F_WRAP64, F_HOP64, F_GEMM64, F_QR_UDV, F_QR_SOLVE, F_ELEM, F_DRIFT,
+enum KFam { F_FLIP32, F_FLIP64, F_WRAP32, F_WRAP64, F_HOP64, F_GEMM64, F_QR_UDV, F_LU_SOLVE, F_ELEM, F_DRIFT,
             F_MEAS, F_COUNT };
 const char *const FAM_NAMES[F_COUNT] = {"flip_f32", "flip_f64", "wrap_f32", "wrap_f64", "hop_f64", "gemm_f64",
-                                        "qr_udv", "qr_solve", "elementwise", "drift_replace", "measure"};
+                                        "qr_udv", "lu_solve", "elementwise", "drift_replace", "measure"};
 
 hipEvent_t take_event(bss_ctx *c) {
   if (!c->pool.empty()) { hipEvent_t e = c->pool.back(); c->pool.pop_back(); return e; }
@@ -519,7 +519,7 @@ struct Exec {
       chk(fresh_prep(RU(b), RD(b), RV(b), I.W1, nullptr, nullptr, I.W3, I.mats, I.N, s));
     }
     if (rhs_v) { Timed tm(c, F_ELEM, s); chk(time_rhs(RD(b), RV(b), I.W3, I.mats, I.N, s)); }
-    { Timed tm(c, F_QR_SOLVE, s); chk(qr_solve_blocked(I.W1, I.W3, I.Tq, I.mats, I.N, s)); }
+    { Timed tm(c, F_LU_SOLVE, s); chk(lu_solve_blocked(I.W1, I.W3, I.mats, I.N, s)); }
     if (left) {
       { Timed tm(c, F_ELEM, s); chk(inv_big(LD(b), I.invb, (long)I.mats * I.N, s)); }
       gemm64(LU(b), false, I.W3, false, out, (long)NN(), (long)NN(), I.invb, I.N);
