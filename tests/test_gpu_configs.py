@@ -351,3 +351,19 @@ def test_rank1_4x4_workload_against_independent_oracle_chains():
     print(f"[gpu] D: GPU {d:.5f} +- {de:.1e}, oracle {od:.5f} +- {ode:.1e} (z = {zd:.2f}); G(tau, k) max z = {zg:.2f}",
           flush=True)
     assert zd < 3.5 and zg < 5.0
+
+
+def test_workload_runner_reports_every_instance():
+    """paper_1504_05090_amd.run on a cut-down multigrid batch (2 chains per
+    instance, 1 + 2 sweeps): one line per instance with its resolved
+    parameters, finite statistics and error bars, then the batch line."""
+    from paper_1504_05090_amd import run
+    print("[gpu] workload runner: C3 with 2 chains, 1 + 2 sweeps", flush=True)
+    rows = run.run("C3", warmup=1, sweeps=2, chains=2)
+    from paper_1504_05090_amd.workloads import CONFIGS
+    assert len(rows) == len(CONFIGS["C3"]["instances"]) + 1
+    for r in rows[:-1]:
+        assert r["chains"] == 2 and r["N"] == r["L"] ** 2 and r["Lambda"] == round(r["beta"] / r["dtau"])
+        assert 0.0 < r["acceptance"] < 1.0 and 0.0 < r["double_occ"] < 0.5
+        assert np.isfinite(r["drift_rel_max"]) and r["gtau_k_err_max"] > 0.0 and r["double_occ_err"] > 0.0
+    assert rows[-1]["workload"] == "C3" and rows[-1]["updates_per_s"] > 0.0
