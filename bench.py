@@ -50,8 +50,8 @@ HBM_PEAK = 8.0e12
 # otherwise null.
 TRAFFIC = {
     "dense": {
-        "qr_udv": (3.9616e9, "k_qr.hip", "321453a5272b"),
-        "lu_solve": (3.3189e9, "k_qr.hip", "321453a5272b"),
+        "qr_udv": (3.9598e9, "k_qr.hip", "d8fb69b09516"),
+        "lu_solve": (3.3189e9, "k_qr.hip", "d8fb69b09516"),
         "flip_f64": (1.1113e9, "k_flip.hip", "f441bb0b7329"),
         "flip_f32": (4.870e8, "k_flip.hip", "f441bb0b7329"),
         # the FP64 NN GEMM kernel (wraps, block products and UDV products share it)

@@ -839,26 +839,26 @@ __global__ __launch_bounds__(QT) void k_qr_udv(double *Xall, double *Tall, long 
   }
 }
 
-// Back substitution U Z = Y in place of Y (B), U upper triangular in M (row
-// i of U in row mrow(i) of M; the identity unless `rowmap` is given), block
-// rows of NB from the bottom: the block row of U right of the diagonal block
-// is staged in LDS for the MFMA update, the diagonal block solved per column.
+// Back substitution U Z = Y in place of Y (B), U upper triangular in M with
+// row i of U in row rowmap[i] of M, block rows of NB from the bottom: the
+// block row of U right of the diagonal block is staged in LDS for the MFMA
+// update, the diagonal block solved per column.
 template <class S>
 __device__ __forceinline__ void back_substitute(const Lds &s, const double *M, double *B, int N, const int *rowmap) {
   constexpr int NB = S::NB;
-  auto mrow = [&](int i) { return rowmap ? rowmap[i] : i; };
+  auto mrow = [&](int i) { return rowmap[i]; };
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int l16 = lane & 15, lq = lane >> 4;
   const int np = (N + NB - 1) / NB;
-  double *Rd = s.T;   // diagonal block of R, [NB][NB]
+  double *Rd = s.T;   // diagonal block of U, [NB][NB]
   // the panel and partial-sum areas (contiguous, free after the factorisation)
-  // hold the block row of R right of the diagonal block; the row stride is
+  // hold the block row of U right of the diagonal block; the row stride is
   // 2 mod 32 doubles so that the MFMA operand reads hit distinct banks
   double *Rs = s.V;
   const int RLD = ((N + 31) / 32) * 32 + 2;
   for (int p = np - 1; p >= 0; --p) {
     const int r0 = p * NB, w = min(NB, N - r0), k0 = r0 + w, kn = N - k0;
-    if (kn > 0) {   // Y_p -= R[r0:r0+w, k0:N] Z[k0:N, :]
+    if (kn > 0) {   // Y_p -= U[r0:r0+w, k0:N] Z[k0:N, :]
 #pragma unroll 8
       for (int e = t; e < NB * kn; e += QT) {
         const int i = e / kn, k = e % kn;
