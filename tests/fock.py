@@ -70,6 +70,23 @@ class Cluster:
         D = sum(self.c[i].T @ self.c[i] @ self.c[i + N].T @ self.c[i + N] for i in range(N)) / N
         return float(np.trace(P[lam] @ D) / np.trace(P[lam]))
 
+    def gtau_exact(self, beta: float, taus, spin: int) -> np.ndarray:
+        """<c_i(tau) c_j^dagger(0)> in continuous imaginary time, H = H_t + H_U
+        with no Trotter split, from the eigenbasis of H: Tr[e^{-(beta-tau)H} c_i
+        e^{-tau H} c_j^dagger] / Z, array [len(taus), N, N] (positive convention)."""
+        E, V = np.linalg.eigh(self.Ht + self.HU)
+        E = E - E.min()
+        Z = np.sum(np.exp(-beta * E))
+        N = self.N
+        C = [V.T @ self.c[i + N * spin] @ V for i in range(N)]
+        out = np.zeros((len(taus), N, N))
+        for a, tau in enumerate(taus):
+            f = np.exp(-(beta - tau) * E)[:, None] * np.exp(-tau * E)[None, :]
+            for i in range(N):
+                for j in range(N):
+                    out[a, i, j] = np.sum(f * C[i] * C[j]) / Z
+        return out
+
     def gtau(self, beta: float, dtau: float, spin: int) -> np.ndarray:
         """<c_i(tau_l) c_j^dagger(0)> = Tr[T^{Lam-l} c_i T^l c_j^dagger] / Z for l = 0..Lam
         (positive convention), array [Lam+1, N, N]."""

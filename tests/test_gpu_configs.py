@@ -367,3 +367,43 @@ def test_workload_runner_reports_every_instance():
         assert 0.0 < r["acceptance"] < 1.0 and 0.0 < r["double_occ"] < 0.5
         assert np.isfinite(r["drift_rel_max"]) and r["gtau_k_err_max"] > 0.0 and r["double_occ_err"] > 0.0
     assert rows[-1]["workload"] == "C3" and rows[-1]["updates_per_s"] > 0.0
+
+
+def test_trotter_elimination_of_gpu_measurements_on_the_2x2_cluster():
+    """The Trotter elimination end to end on GPU data: 2 x 2, U = 2, beta = 2,
+    dtau = 0.25, 0.2, 0.125, 0.1 as one batch (512 chains each, 100 + 300
+    sweeps); the measured G(tau_l, k) of each grid goes through
+    bss_trotter_extrapolate.  The reference is the same extrapolation of the
+    exact Trotterised values (Fock space), which is within 1e-4 of the exact
+    continuous-time G(tau, k): the GPU's result agrees with it within 4.5
+    standard errors, propagated exactly through the extrapolation's
+    coefficients (it is linear in its data)."""
+    from tests.fock import Cluster
+    from tests.fock_gk import continuous_gk, trotterised_gk
+    L, U, beta = 2, 2.0, 2.0
+    dts = [0.25, 0.2, 0.125, 0.1]
+    print("[gpu] Trotter elimination: 2x2 U=2 beta=2, 4 grids x 512 chains, 100 + 300 sweeps", flush=True)
+    g = bss.Context([dict(L=L, U=U, t=T, beta=beta, dtau=dt, seed=BASE_SEED, n_chains=512) for dt in dts],
+                    precision="fp64")
+    g.sweep(100)
+    g.sweep(300, measure=True)
+    means, errs = zip(*[g.gtau_k(j) for j in range(len(dts))])
+    tau_f = np.linspace(0.0, beta, 21)
+    got = bss.trotter_extrapolate(dts, list(means), beta, tau_f)
+    # coefficients of each input row: the extrapolation of unit rows
+    var = np.zeros_like(got)
+    for a, G in enumerate(means):
+        n = G.shape[0]
+        unit = [np.eye(n) if b == a else np.zeros((means[b].shape[0], n)) for b in range(len(dts))]
+        coef = bss.trotter_extrapolate(dts, unit, beta, tau_f)          # [n_tau_f, n]
+        var += (coef ** 2) @ (errs[a] ** 2)
+    sd = np.sqrt(var)
+    cl = Cluster(L, T, U)
+    ref = bss.trotter_extrapolate(dts, [trotterised_gk(cl, beta, dt) for dt in dts], beta, tau_f)
+    exact = continuous_gk(cl, beta, tau_f)
+    z = np.abs(got - ref) / np.maximum(sd, 1e-12)
+    print(f"[gpu] extrapolated G(tau, k): max z = {np.max(z):.2f} (max sd {np.max(sd):.1e}); "
+          f"reference vs continuous time {np.max(np.abs(ref - exact)):.1e}; "
+          f"GPU vs continuous time {np.max(np.abs(got - exact)):.1e}", flush=True)
+    assert np.max(np.abs(ref - exact)) < 1e-4
+    assert np.max(z) < 4.5
