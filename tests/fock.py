@@ -87,6 +87,29 @@ class Cluster:
                     out[a, i, j] = np.sum(f * C[i] * C[j]) / Z
         return out
 
+    def giw_exact(self, beta: float, n_freq: int, spin: int) -> np.ndarray:
+        """G_ij(i w_n) = int_0^beta e^{i w_n tau} G_ij(tau) dtau in the sign of
+        eq. (4), G(tau) = -<c_i(tau) c_j^dagger>, w_n = (2n+1) pi / beta, from
+        the Lehmann sum over the eigenstates of H = H_t + H_U:
+        (1/Z) sum_mn (e^{-beta E_m} + e^{-beta E_n}) <m|c_i|n><n|c_j^dagger|m>
+        / (i w_n + E_m - E_n); array [n_freq, N, N] (complex)."""
+        E, V = np.linalg.eigh(self.Ht + self.HU)
+        E = E - E.min()
+        w = np.exp(-beta * E)
+        Z = np.sum(w)
+        N = self.N
+        C = [V.T @ self.c[i + N * spin] @ V for i in range(N)]
+        wn = (2 * np.arange(n_freq) + 1) * np.pi / beta
+        out = np.zeros((n_freq, N, N), dtype=complex)
+        occ = (w[:, None] + w[None, :]) / Z
+        dE = E[:, None] - E[None, :]
+        for a, x in enumerate(wn):
+            den = occ / (1j * x + dE)
+            for i in range(N):
+                for j in range(N):
+                    out[a, i, j] = np.sum(den * C[i] * C[j])
+        return out
+
     def gtau(self, beta: float, dtau: float, spin: int) -> np.ndarray:
         """<c_i(tau_l) c_j^dagger(0)> = Tr[T^{Lam-l} c_i T^l c_j^dagger] / Z for l = 0..Lam
         (positive convention), array [Lam+1, N, N]."""

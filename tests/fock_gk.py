@@ -31,3 +31,18 @@ def trotterised_gk(cl: Cluster, beta: float, dtau: float) -> np.ndarray:
 
 def continuous_gk(cl: Cluster, beta: float, taus) -> np.ndarray:
     return to_gk([cl.gtau_exact(beta, taus, s) for s in range(2)], cl.L)
+
+
+def continuous_giw_k(cl: Cluster, beta: float, n_freq: int) -> np.ndarray:
+    """G_k(i w_n) [n_freq, N] of the continuous-time model in the same
+    cos(k (r_i - r_j)) form, averaged over the spins (Lehmann sums)."""
+    L, N = cl.L, cl.N
+    g = [cl.giw_exact(beta, n_freq, s) for s in range(2)]
+    out = np.zeros((n_freq, N), dtype=complex)
+    for k in range(N):
+        kx, ky = 2 * math.pi * (k % L) / L, 2 * math.pi * (k // L) / L
+        ph = np.array([[math.cos(kx * ((i % L) - (j % L)) + ky * ((i // L) - (j // L))) for j in range(N)]
+                       for i in range(N)])
+        for a in range(n_freq):
+            out[a, k] = 0.5 * sum(np.sum(ph * g[s][a]) for s in range(2)) / N
+    return out
