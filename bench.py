@@ -52,8 +52,8 @@ TRAFFIC = {
     "dense": {
         "qr_udv": (3.9598e9, "k_qr.hip", "d8fb69b09516"),
         "lu_solve": (3.3189e9, "k_qr.hip", "d8fb69b09516"),
-        "flip_f64": (1.1113e9, "k_flip.hip", "f441bb0b7329"),
-        "flip_f32": (4.870e8, "k_flip.hip", "f441bb0b7329"),
+        "flip_f64": (1.1113e9, "k_flip.hip", "dad164a0efd0"),
+        "flip_f32": (4.870e8, "k_flip.hip", "dad164a0efd0"),
         # the FP64 NN GEMM kernel (wraps, block products and UDV products share it)
         "wrap_f64": (4.503e8, "k_gemm.hip", "57c2c9444073"),
         "gemm_f64": (4.503e8, "k_gemm.hip", "57c2c9444073"),

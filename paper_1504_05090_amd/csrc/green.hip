@@ -155,7 +155,7 @@ bss_status bss_green_from_field(int32_t L, double U, double t, double beta, doub
   hipError_t e = bss::green_run(L, U, t, beta, dtau, n_stab, l, field, G_out, base, s);
   // the scratch is freed once the work on the stream has finished
   const hipError_t e2 = hipStreamSynchronize(s);
-  hipFree(base);
+  (void)hipFree(base);
   if (e == hipSuccess) e = e2;
   return e == hipSuccess ? BSS_OK : BSS_E_DEVICE;
 }

@@ -300,9 +300,6 @@ struct PairLanes {
 
 // value held by the other lane of the site (lane ^ 16): swizzle swapping the
 // two rows of each 32-lane half
-__device__ __forceinline__ float pair_partner(float v) {
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
-}
 __device__ __forceinline__ double pair_partner(double v) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_ds_swizzle((int)(b & 0xffffffffll), 0x401F);

@@ -176,13 +176,14 @@ struct Timed {
   hipStream_t s;
   hipEvent_t a = nullptr;
   Timed(bss_ctx *c_, int f, hipStream_t s_) : c(c_), fam(f), s(s_) {
-    if (c->profile && (a = take_event(c))) hipEventRecord(a, s);
+    // (a failed record surfaces in bss_get_profile's elapsed-time query)
+    if (c->profile && (a = take_event(c))) (void)hipEventRecord(a, s);
   }
   ~Timed() {
     if (!a) return;
     hipEvent_t b = take_event(c);
     if (!b) { c->pool.push_back(a); return; }
-    hipEventRecord(b, s);
+    (void)hipEventRecord(b, s);
     c->fam[fam].pending.push_back({a, b});
   }
 };
@@ -923,9 +924,9 @@ bool capture_range(bss_ctx *c, int l_from, int l_to, hipGraphExec_t *out) {
   }
   hipGraphExec_t ex = nullptr;
   if (ok) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
-  if (g) hipGraphDestroy(g);
+  if (g) (void)hipGraphDestroy(g);
   if (!ok && ex) {
-    hipGraphExecDestroy(ex);
+    (void)hipGraphExecDestroy(ex);
     ex = nullptr;
   }
   *out = ex;
@@ -946,10 +947,10 @@ bool capture_range(bss_ctx *c, int l_from, int l_to, hipGraphExec_t *out) {
 // direct launches.
 void release_graph(bss_ctx::SweepGraph &sg) {
   for (auto &g : sg.g)
-    if (g) { hipGraphExecDestroy(g); g = nullptr; }
-  if (sg.ev_fork) { hipEventDestroy(sg.ev_fork); sg.ev_fork = nullptr; }
+    if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+  if (sg.ev_fork) { (void)hipEventDestroy(sg.ev_fork); sg.ev_fork = nullptr; }
   for (auto &e : sg.ev)
-    if (e) { hipEventDestroy(e); e = nullptr; }
+    if (e) { (void)hipEventDestroy(e); e = nullptr; }
 }
 
 bool capture_sweep(bss_ctx *c, bss_ctx::SweepGraph &sg) {
@@ -1749,8 +1750,8 @@ bss_status run_trial(const bss_instance &in0, bss_options o, const std::vector<c
   bss_stats s{};
   if (st == BSS_OK) st = bss_get_stats(c, 0, &s);   // synchronises
   if (st == BSS_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BSS_E_DEVICE;
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   bss_destroy(c);
   t.m32 = s.fp32_slices;
   if (st == BSS_E_NUMERICAL || st == BSS_E_STATE) {   // the chain broke down: out of bound
@@ -1880,24 +1881,25 @@ void bss_destroy(bss_ctx *c) {
   if (!c) return;
   // everything finished first, then the graphs (and their events), then the
   // events and streams of direct launches, then the memory
-  if (c->stream) hipStreamSynchronize(c->stream);
+  // (teardown: a failure here has nothing left to report to)
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (auto &I : c->sh) {
-    if (I.s) hipStreamSynchronize(I.s);
-    if (I.aux) hipStreamSynchronize(I.aux);
+    if (I.s) (void)hipStreamSynchronize(I.s);
+    if (I.aux) (void)hipStreamSynchronize(I.aux);
   }
   destroy_graphs(c);
   for (auto &I : c->sh) {
-    if (I.s) hipStreamDestroy(I.s);
-    if (I.aux) hipStreamDestroy(I.aux);
-    if (I.ev_main) hipEventDestroy(I.ev_main);
-    if (I.ev_left) hipEventDestroy(I.ev_left);
+    if (I.s) (void)hipStreamDestroy(I.s);
+    if (I.aux) (void)hipStreamDestroy(I.aux);
+    if (I.ev_main) (void)hipEventDestroy(I.ev_main);
+    if (I.ev_left) (void)hipEventDestroy(I.ev_left);
   }
   for (auto &f : c->fam)
-    for (auto &p : f.pending) { hipEventDestroy(p.first); hipEventDestroy(p.second); }
-  for (auto e : c->pool) hipEventDestroy(e);
-  if (c->ev_fork) hipEventDestroy(c->ev_fork);
-  if (c->own_mem && c->mem) hipFree(c->mem);
-  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+    for (auto &p : f.pending) { (void)hipEventDestroy(p.first); (void)hipEventDestroy(p.second); }
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->own_mem && c->mem) (void)hipFree(c->mem);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
