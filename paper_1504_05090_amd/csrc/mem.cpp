@@ -19,11 +19,19 @@
 // condition alpha u + Sigma V^T (C a - d) = 0 is solved by Newton's method
 // (its Jacobian has eigenvalues >= alpha), with backtracking on the squared
 // residual; once the Newton step is at most 1e-8 the full step is taken and
-// the iteration ends (the quadratic phase leaves an error of order 1e-16).  The historic alpha is the root of
-// chi^2(alpha) - n in ln alpha (chi^2 grows with alpha), bracketed by
-// decades downwards from alpha = 1e12 to at most 1e-8 and found by regula
-// falsi with the Illinois modification, each solve starting from the
-// nearest solution already found.
+// the iteration ends (the quadratic phase leaves an error of order 1e-16).
+// The stationary point is unique (Q is strictly convex in a, and F = 0 makes
+// the whole gradient of Q in ln a vanish) and moves smoothly with alpha (the
+// Jacobian stays invertible), but a start far from it can leave damped
+// Newton crawling through the exponential (steps cut to 1e-3).  So solves
+// follow the path in ln alpha: from the nearest solution already found, and
+// if that does not converge, from solutions at intermediate alphas (the
+// step in ln alpha halved on failure and doubled again on success).  A
+// fixed alpha whose solve from u = 0 fails is reached from alpha = 1e12,
+// where u = 0 is close.  The historic alpha is the root of chi^2(alpha) - n
+// in ln alpha (chi^2 grows with alpha), bracketed by decades downwards from
+// alpha = 1e12 to at most 1e-8 and found by regula falsi with the Illinois
+// modification.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -83,6 +91,7 @@ struct Mem {
   std::vector<double> U;    // [M][s]  left singular vectors of C^T (columns)
   // per-iterate work
   std::vector<double> z, a, r, h;
+  double Qscale = 0;   // sum of the magnitudes of Q's terms (its rounding is ~eps Qscale)
 
   // Thin SVD of C^T (M x n) by one-sided Jacobi on its n columns: rotate
   // pairs of columns until all are orthogonal to working precision; the
@@ -133,7 +142,7 @@ struct Mem {
   bool eval(const std::vector<double> &u, double alpha, double &Q) {
     z.assign(M, 0.0);
     a.resize(M);
-    double ent = 0.0;
+    double ent = 0.0, ent_mag = 0.0;
     for (int j = 0; j < M; ++j) {
       double v = 0;
       for (int k = 0; k < s; ++k) v += U[(size_t)j * s + k] * u[k];
@@ -141,6 +150,7 @@ struct Mem {
       a[j] = mu[j] * std::exp(v);
       if (!(a[j] > 1e-290) || !std::isfinite(a[j])) return false;
       ent += a[j] - mu[j] - a[j] * v;
+      ent_mag += a[j] + mu[j] + std::fabs(a[j] * v);
     }
     r.resize(n);
     double chi2 = 0.0;
@@ -151,6 +161,7 @@ struct Mem {
       chi2 += v * v;
     }
     Q = 0.5 * chi2 - alpha * ent;
+    Qscale = 0.5 * chi2 + alpha * ent_mag;
     return std::isfinite(Q);
   }
 
@@ -164,8 +175,14 @@ struct Mem {
   // F(u) = U^T (C^T r + alpha U u) = alpha u + Sigma V^T r (U^T C^T = Sigma V^T
   // holds also for the truncated SVD), whose Jacobian
   // J = alpha I + (C U)^T C diag(a) U = alpha I + Sigma^2 U^T diag(a) U has
-  // eigenvalues >= alpha, so the Newton step is defined for every a > 0 and
-  // descends on the merit phi = |F|^2 / 2.  false: no convergence.
+  // eigenvalues >= alpha, so the Newton step du = -J^-1 F is defined for
+  // every a > 0.  It descends on Q itself: with T = U^T diag(a) U (SPD) the
+  // gradient of Q in u is T F and J = alpha I + Sigma^2 T, so
+  // grad Q . du = -F^T (alpha T^-1 + Sigma^2)^-1 F < 0; and the only
+  // stationary point of Q in u is the minimiser.  The step is therefore
+  // backtracked on Q (Armijo, within Q's rounding), which unlike |F|^2 does
+  // not stall where the exponential makes F far from linear.  false: no
+  // convergence.
   bool solve(double alpha, std::vector<double> &u) {
     double Q;
     if (!eval(u, alpha, Q)) return false;
@@ -179,7 +196,7 @@ struct Mem {
     }
     std::vector<double> F(s), Fn(s), J((size_t)s * s), P((size_t)n * s), du(s), un(s);
     residual_F(alpha, F);
-    double phi = 0.5 * dot(F, F);
+    double phi = 0.5 * dot(F, F), Qc = Q, Qsc = Qscale;
     for (int it = 0; it < 500; ++it) {
       // J = alpha I + R^T P, P = C diag(a) U
       for (int i = 0; i < n; ++i)
@@ -211,21 +228,61 @@ struct Mem {
         else if (!eval(u, alpha, Q)) return false;
         return true;
       }
-      double t = 1.0, phin = 0.0;
+      // slope of Q along du: (U F)^T diag(a) (U du), a at the current u
+      double slope = 0.0;
+      for (int j = 0; j < M; ++j) {
+        double uf = 0.0, ud = 0.0;
+        for (int k = 0; k < s; ++k) {
+          uf += U[(size_t)j * s + k] * F[k];
+          ud += U[(size_t)j * s + k] * du[k];
+        }
+        slope += a[j] * uf * ud;
+      }
+      slope = std::min(slope, 0.0);
+      double t = 1.0;
       bool accepted = false;
       for (; t >= 1e-30; t *= 0.5) {
         for (int k = 0; k < s; ++k) un[k] = u[k] + t * du[k];
         if (!eval(un, alpha, Q)) continue;
-        residual_F(alpha, Fn);
-        phin = 0.5 * dot(Fn, Fn);
-        if (phin <= (1.0 - 2e-4 * t) * phi) { accepted = true; break; }
+        const double tol = 1e-13 * std::max(Qsc, Qscale);
+        if (Q <= Qc + 1e-4 * t * slope + tol) { accepted = true; break; }
       }
       if (!accepted) return false;
       u = un;
-      F = Fn;
-      phi = phin;
+      Qc = Q;
+      Qsc = Qscale;
+      residual_F(alpha, F);
+      phi = 0.5 * dot(F, F);
     }
     return false;
+  }
+
+  // The solution at ln alpha = lt (left in u, a, r) from u0, the solution at
+  // ln alpha = l0: Newton from the last solution reached, towards lt in
+  // steps of ln alpha that halve on failure (at most 40 times) and double
+  // on success up to the whole distance.  false: the path was lost.
+  bool track(double l0, const std::vector<double> &u0, double lt, std::vector<double> &u) {
+    if (l0 == lt) {
+      u = u0;
+      return solve(std::exp(lt), u);
+    }
+    std::vector<double> cur = u0;
+    double l = l0, h = lt - l0;
+    const double hmax = std::fabs(h);
+    int cuts = 0;
+    while (l != lt) {
+      const double ln = std::fabs(lt - l) <= std::fabs(h) ? lt : l + h;
+      u = cur;
+      if (solve(std::exp(ln), u)) {
+        cur = u;
+        l = ln;
+        if (2.0 * std::fabs(h) <= hmax) h *= 2.0;
+      } else {
+        if (++cuts > 40) return false;
+        h *= 0.5;
+      }
+    }
+    return true;
   }
 
   std::vector<double> R;    // [n][s] C U
@@ -288,25 +345,32 @@ bss_status bss_mem_spectrum(int32_t n_tau, const double *tau, const double *G, c
   for (int j = 0; j < n_omega; ++j) P.mu[j] = q[j] * model[j];
   P.svd();
   if (P.s < 1) return BSS_E_NUMERICAL;
+  const double ln10 = std::log(10.0), lmin = std::log(1e-8), lmax = std::log(1e12);
   std::vector<double> u(P.s, 0.0);
   if (alpha > 0.0) {
-    if (!P.solve(alpha, u)) return BSS_E_NUMERICAL;
+    if (!P.solve(alpha, u)) {
+      std::vector<double> u0(P.s, 0.0);
+      if (!P.solve(std::exp(lmax), u0) || !P.track(lmax, u0, std::log(alpha), u)) return BSS_E_NUMERICAL;
+    }
   } else {
     // historic alpha: chi^2(alpha) = n_tau, chi^2 increasing in alpha
-    const double target = n_tau, ln10 = std::log(10.0), lmin = std::log(1e-8), lmax = std::log(1e12);
-    auto f = [&](double la, std::vector<double> &uu, double &val) {
-      if (!P.solve(std::exp(la), uu)) return false;
+    const double target = n_tau;
+    // uu: in, the solution at ln alpha = lf; out, the one at la
+    auto f = [&](double lf, double la, std::vector<double> &uu, double &val) {
+      std::vector<double> from = uu;
+      if (!P.track(lf, from, la, uu)) return false;
       val = P.chi2() - target;
       return true;
     };
     double hi = lmax, lo, flo, fhi;
     std::vector<double> ulo, uhi(P.s, 0.0);
-    if (!f(hi, uhi, fhi)) return BSS_E_NUMERICAL;
+    if (!P.solve(std::exp(hi), uhi)) return BSS_E_NUMERICAL;
+    fhi = P.chi2() - target;
     if (fhi < 0.0) return BSS_E_NUMERICAL;   // chi^2 < n already at the largest alpha
     ulo = uhi;
     lo = hi - ln10;
     for (;;) {
-      if (!f(lo, ulo, flo)) return BSS_E_NUMERICAL;
+      if (!f(hi, lo, ulo, flo)) return BSS_E_NUMERICAL;
       if (flo < 0.0) break;
       hi = lo; fhi = flo; uhi = ulo;
       lo -= ln10;
@@ -319,9 +383,10 @@ bss_status bss_mem_spectrum(int32_t n_tau, const double *tau, const double *G, c
     for (int it = 0; it < 200; ++it) {
       la = (lo * fhi - hi * flo) / (fhi - flo);
       if (!(la > lo && la < hi)) la = 0.5 * (lo + hi);
-      u = (la - lo < hi - la) ? ulo : uhi;
+      const bool near_lo = la - lo < hi - la;
+      u = near_lo ? ulo : uhi;
       double fm;
-      if (!f(la, u, fm)) return BSS_E_NUMERICAL;
+      if (!f(near_lo ? lo : hi, la, u, fm)) return BSS_E_NUMERICAL;
       if (std::fabs(fm) <= 1e-12 * target || hi - lo <= 1e-14 * std::max(1.0, std::fabs(la))) break;
       if (fm < 0.0) {
         lo = la; flo = fm; ulo = u;

@@ -46,3 +46,28 @@ def continuous_giw_k(cl: Cluster, beta: float, n_freq: int) -> np.ndarray:
         for a in range(n_freq):
             out[a, k] = 0.5 * sum(np.sum(ph * g[s][a]) for s in range(2)) / N
     return out
+
+
+def spectral_moments_k(cl: Cluster, beta: float, pmax: int) -> np.ndarray:
+    """int w^p A_k(w) dw for p = 0..pmax, array [pmax + 1, N], averaged over
+    the spins, A_k the spectral function whose eq. (4) transform is G(tau, k):
+    the thermal expectation <{X_p, c_k^dagger}> with X_0 = c_k and
+    X_{p+1} = [X_p, H], c_k = N^-1/2 sum_i e^{-i k r_i} c_i (the frequency
+    moments of A follow from the time derivatives of the anticommutator
+    function at t = 0)."""
+    L, N = cl.L, cl.N
+    H = cl.Ht + cl.HU
+    E, V = np.linalg.eigh(H)
+    w = np.exp(-beta * (E - E.min()))
+    rho = (V * (w / w.sum())) @ V.T
+    out = np.zeros((pmax + 1, N))
+    for k in range(N):
+        kx, ky = 2 * math.pi * (k % L) / L, 2 * math.pi * (k // L) / L
+        for s in range(2):
+            ck = sum(np.exp(-1j * (kx * (i % L) + ky * (i // L))) * cl.c[i + N * s] for i in range(N)) / math.sqrt(N)
+            cd = ck.conj().T
+            X = ck
+            for p in range(pmax + 1):
+                out[p, k] += 0.5 * np.real(np.trace(rho @ (X @ cd + cd @ X)))
+                X = X @ H - H @ X
+    return out
