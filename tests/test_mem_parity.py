@@ -53,6 +53,48 @@ def test_fixed_alpha_parity(alpha, n_tau, n_w, noise):
     compare(tau, G, sig, w, m, alpha)
 
 
+def cluster_draws():
+    """G(tau, k) of the 2 x 2 Hubbard cluster (U = 2, t = 0.25, beta = 2) in
+    continuous time from its Fock space, on 41 points, with N(0, 1e-4^2)
+    noise, at k = (pi, 0), (0, 0), (pi, pi) (a spectrum of a few sharp
+    lines, unlike the smooth synthetic ones above)."""
+    from tests.fock import Cluster
+    from tests.fock_gk import continuous_gk
+    tau = np.linspace(0.0, 2.0, 41)
+    G = continuous_gk(Cluster(2, 0.25, 2.0), 2.0, tau)
+    sig = np.full(tau.size, 1e-4)
+    rng = np.random.default_rng(5)
+    return tau, sig, {k: G[:, k] + sig * rng.standard_normal(tau.size) for k in (1, 0, 3)}
+
+
+@pytest.mark.parametrize("alpha", [1e4, 1e2, 1.0, 1e-2])
+def test_fixed_alpha_parity_on_cluster_spectra(alpha):
+    """Both solvers reach the same A at every alpha from 1e4 down to 1e-2,
+    to a relative 1e-10 (1 + 100 / alpha) on the A_j above 1e-6 of the peak:
+    the Jacobian's smallest eigenvalue is alpha, so the rounding floor of the
+    gradient moves A by about 1/alpha (measured 3e-13 at 1e4, 3e-9 at 1,
+    1.1e-7 at 1e-2).  Where the data ask for lines sharper than the double
+    range allows (alpha = 1e-2 at k = (pi, 0) and (pi, pi)), both report it."""
+    tau, sig, draws = cluster_draws()
+    w = np.linspace(-4.0, 4.0, 161)
+    m = np.full(w.size, 1.0 / 8.0)
+    for k, G in draws.items():
+        if alpha < 0.1 and k != 0:
+            with pytest.raises(bss.BssError) as err:
+                bss.mem_spectrum(tau, G, sig, 2.0, w, m, alpha)
+            assert err.value.status == bss.BSS_E_NUMERICAL
+            with pytest.raises(RuntimeError):
+                mem.spectrum(tau, G, sig, 2.0, w, m, alpha)
+            continue
+        Al, _, cl = bss.mem_spectrum(tau, G, sig, 2.0, w, m, alpha)
+        Ao, _, co = mem.spectrum(tau, G, sig, 2.0, w, m, alpha)
+        big = Ao > 1e-6 * Ao.max()
+        tol = 1e-10 * (1.0 + 100.0 / alpha)
+        assert np.max(np.abs(Al - Ao)[big] / Ao[big]) < tol, k
+        assert np.max(np.abs(Al - Ao)) < tol * Ao.max(), k
+        assert cl == pytest.approx(co, rel=1e-9)
+
+
 def test_nonuniform_grids_and_per_point_errors():
     """A denser w grid near 0, tau points clustered at the ends (where
     G(tau) varies fastest) and errors that differ per point."""
