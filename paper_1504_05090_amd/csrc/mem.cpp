@@ -17,21 +17,13 @@
 // Jacobi, singular values below max(n, M) eps sigma_max dropped) the unknown is
 // u in a = mu exp(U u), s = rank(C) numbers instead of M.  The stationarity
 // condition alpha u + Sigma V^T (C a - d) = 0 is solved by Newton's method
-// (its Jacobian has eigenvalues >= alpha), with backtracking on the squared
-// residual; once the Newton step is at most 1e-8 the full step is taken and
+// (its Jacobian has eigenvalues >= alpha), with backtracking on Q itself
+// (the Newton step descends on it); once the Newton step is at most 1e-8 the full step is taken and
 // the iteration ends (the quadratic phase leaves an error of order 1e-16).
-// The stationary point is unique (Q is strictly convex in a, and F = 0 makes
-// the whole gradient of Q in ln a vanish) and moves smoothly with alpha (the
-// Jacobian stays invertible), but a start far from it can leave damped
-// Newton crawling through the exponential (steps cut to 1e-3).  So solves
-// follow the path in ln alpha: from the nearest solution already found, and
-// if that does not converge, from solutions at intermediate alphas (the
-// step in ln alpha halved on failure and doubled again on success).  A
-// fixed alpha whose solve from u = 0 fails is reached from alpha = 1e12,
-// where u = 0 is close.  The historic alpha is the root of chi^2(alpha) - n
-// in ln alpha (chi^2 grows with alpha), bracketed by decades downwards from
-// alpha = 1e12 to at most 1e-8 and found by regula falsi with the Illinois
-// modification.
+// The historic alpha is the root of chi^2(alpha) - n in ln alpha (chi^2
+// grows with alpha), bracketed by decades downwards from alpha = 1e12 to at
+// most 1e-8 and found by regula falsi with the Illinois modification, each
+// solve starting from the nearest solution already found.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -257,34 +249,6 @@ struct Mem {
     return false;
   }
 
-  // The solution at ln alpha = lt (left in u, a, r) from u0, the solution at
-  // ln alpha = l0: Newton from the last solution reached, towards lt in
-  // steps of ln alpha that halve on failure (at most 40 times) and double
-  // on success up to the whole distance.  false: the path was lost.
-  bool track(double l0, const std::vector<double> &u0, double lt, std::vector<double> &u) {
-    if (l0 == lt) {
-      u = u0;
-      return solve(std::exp(lt), u);
-    }
-    std::vector<double> cur = u0;
-    double l = l0, h = lt - l0;
-    const double hmax = std::fabs(h);
-    int cuts = 0;
-    while (l != lt) {
-      const double ln = std::fabs(lt - l) <= std::fabs(h) ? lt : l + h;
-      u = cur;
-      if (solve(std::exp(ln), u)) {
-        cur = u;
-        l = ln;
-        if (2.0 * std::fabs(h) <= hmax) h *= 2.0;
-      } else {
-        if (++cuts > 40) return false;
-        h *= 0.5;
-      }
-    }
-    return true;
-  }
-
   std::vector<double> R;    // [n][s] C U
 
   // F = U^T (C^T r + alpha z) from the current iterate
@@ -345,32 +309,25 @@ bss_status bss_mem_spectrum(int32_t n_tau, const double *tau, const double *G, c
   for (int j = 0; j < n_omega; ++j) P.mu[j] = q[j] * model[j];
   P.svd();
   if (P.s < 1) return BSS_E_NUMERICAL;
-  const double ln10 = std::log(10.0), lmin = std::log(1e-8), lmax = std::log(1e12);
   std::vector<double> u(P.s, 0.0);
   if (alpha > 0.0) {
-    if (!P.solve(alpha, u)) {
-      std::vector<double> u0(P.s, 0.0);
-      if (!P.solve(std::exp(lmax), u0) || !P.track(lmax, u0, std::log(alpha), u)) return BSS_E_NUMERICAL;
-    }
+    if (!P.solve(alpha, u)) return BSS_E_NUMERICAL;
   } else {
     // historic alpha: chi^2(alpha) = n_tau, chi^2 increasing in alpha
-    const double target = n_tau;
-    // uu: in, the solution at ln alpha = lf; out, the one at la
-    auto f = [&](double lf, double la, std::vector<double> &uu, double &val) {
-      std::vector<double> from = uu;
-      if (!P.track(lf, from, la, uu)) return false;
+    const double target = n_tau, ln10 = std::log(10.0), lmin = std::log(1e-8), lmax = std::log(1e12);
+    auto f = [&](double la, std::vector<double> &uu, double &val) {
+      if (!P.solve(std::exp(la), uu)) return false;
       val = P.chi2() - target;
       return true;
     };
     double hi = lmax, lo, flo, fhi;
     std::vector<double> ulo, uhi(P.s, 0.0);
-    if (!P.solve(std::exp(hi), uhi)) return BSS_E_NUMERICAL;
-    fhi = P.chi2() - target;
+    if (!f(hi, uhi, fhi)) return BSS_E_NUMERICAL;
     if (fhi < 0.0) return BSS_E_NUMERICAL;   // chi^2 < n already at the largest alpha
     ulo = uhi;
     lo = hi - ln10;
     for (;;) {
-      if (!f(hi, lo, ulo, flo)) return BSS_E_NUMERICAL;
+      if (!f(lo, ulo, flo)) return BSS_E_NUMERICAL;
       if (flo < 0.0) break;
       hi = lo; fhi = flo; uhi = ulo;
       lo -= ln10;
@@ -383,10 +340,9 @@ bss_status bss_mem_spectrum(int32_t n_tau, const double *tau, const double *G, c
     for (int it = 0; it < 200; ++it) {
       la = (lo * fhi - hi * flo) / (fhi - flo);
       if (!(la > lo && la < hi)) la = 0.5 * (lo + hi);
-      const bool near_lo = la - lo < hi - la;
-      u = near_lo ? ulo : uhi;
+      u = (la - lo < hi - la) ? ulo : uhi;
       double fm;
-      if (!f(near_lo ? lo : hi, la, u, fm)) return BSS_E_NUMERICAL;
+      if (!f(la, u, fm)) return BSS_E_NUMERICAL;
       if (std::fabs(fm) <= 1e-12 * target || hi - lo <= 1e-14 * std::max(1.0, std::fabs(la))) break;
       if (fm < 0.0) {
         lo = la; flo = fm; ulo = u;

@@ -74,8 +74,8 @@ def test_mem_spectrum_of_the_exact_g_keeps_the_sum_rules():
     ones within 2e-3, 2e-2 and 6e-2 (the weight is fixed by G(0) + G(beta)
     through eq. (4), the higher moments less tightly by the data; measured
     errors 4e-4, 6e-3, 3e-2).  The noise draw for k = (0, 0) is the one on
-    which a search that restarted each solve from the previous alpha's
-    solution stalled."""
+    which the library's search stalled while its Newton steps were
+    backtracked on |F|^2 instead of Q."""
     cl = Cluster(2, T, U)
     mom = spectral_moments_k(cl, BETA, 2)
     for k in range(4):

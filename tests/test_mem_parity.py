@@ -5,8 +5,7 @@ without a GPU.
 The two share only the readings: the library solves the stationarity
 condition in the singular space of the kernel (one-sided Jacobi SVD, Newton
 on alpha u + Sigma V^T r = 0, backtracked on Q) and finds the historic alpha
-by regula falsi, each solve following the path in ln alpha from the nearest
-solution already found; the oracle runs Newton's method on Q in A itself and
+by regula falsi with warm starts; the oracle runs Newton's method on Q in A itself and
 scipy's Brent root finder with every alpha solved from the default model.
 The minimiser of Q is unique, so both must land on it to the rounding floor
 of the gradient (about 1e-9 relative in A for these data)."""
