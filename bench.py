@@ -50,8 +50,8 @@ HBM_PEAK = 8.0e12
 # otherwise null.
 TRAFFIC = {
     "dense": {
-        "qr_udv": (3.9598e9, "k_qr.hip", "d8fb69b09516"),
-        "lu_solve": (3.3189e9, "k_qr.hip", "d8fb69b09516"),
+        "qr_udv": (3.9631e9, "k_qr.hip", "758a4ba99fd6"),
+        "lu_solve": (3.3188e9, "k_qr.hip", "758a4ba99fd6"),
         "flip_f64": (1.1113e9, "k_flip.hip", "dad164a0efd0"),
         "flip_f32": (4.870e8, "k_flip.hip", "dad164a0efd0"),
         # the FP64 NN GEMM kernel (wraps, block products and UDV products share it)

@@ -205,10 +205,17 @@ __device__ __forceinline__ int panel_factor(const Lds &s, int m, int w, int *swp
     const int q = j + 1 + qo;
     double a1 = 0.0, head = 0.0;   // norms of column q over rows > j+1 and its row j+1
     if (q < w) {
-      // four rows per iteration: their loads are issued together, the sums
-      // keep the row order
+      // eight, then four rows per iteration: their loads are issued
+      // together, the sums keep the row order
       double acc = (sub == 0) ? s.V[j * LDV + q] : 0.0;
       int r = j + 1 + sub;
+      for (; r + 56 < m; r += 64) {
+        double x[8], c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) { x[u] = s.V[(r + 8 * u) * LDV + j] * scale; c[u] = s.V[(r + 8 * u) * LDV + q]; }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += x[u] * c[u];
+      }
       for (; r + 24 < m; r += 32) {
         double x[4], c[4];
 #pragma unroll
@@ -221,6 +228,17 @@ __device__ __forceinline__ int panel_factor(const Lds &s, int m, int w, int *swp
       const double f = tj * acc;
       if (sub == 0) s.V[j * LDV + q] -= f;
       r = j + 1 + sub;
+      for (; r + 56 < m; r += 64) {
+        double x[8], c[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) { x[u] = s.V[(r + 8 * u) * LDV + j] * scale; c[u] = s.V[(r + 8 * u) * LDV + q]; }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const double v = c[u] - f * x[u];
+          s.V[(r + 8 * u) * LDV + q] = v;
+          if (r + 8 * u > j + 1) a1 += v * v; else head = v;
+        }
+      }
       for (; r + 24 < m; r += 32) {
         double x[4], c[4];
 #pragma unroll
